@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Benchmark of the RPA energy-density hot path on one MI355X.
+
+One step = one batch of 64 Lanczos start vectors (8 coarse points x 8
+frequencies) through the whole path: nu^1/2 -> Galerkin guess -> batched
+Sternheimer COCG (FP32 + FP64 refinement) -> density accumulation -> nu^1/2 ->
+Lanczos recurrence with full reorthogonalisation -> tridiagonal quadrature,
+then tricubic interpolation of the resident coarse field and frequency
+integration.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "RPA energy-density points/s, Si64 FP32+refine vs FP64; stencil GB/s; p99 latency"
+HBM_PEAK_GBPS = 8000.0
+
+# workload name -> synthetic cell preset and method settings
+WORKLOADS = {
+    "si64": dict(preset="si64", n_lanczos=8, tol=1e-6, stride=2, interp="tricubic", every=3,
+                 pts_per_step=8, desc="Si64-like 2x2x2 cell, 48^3 grid, 128 orbitals"),
+    "si8": dict(preset="si8", n_lanczos=8, tol=1e-6, stride=2, interp="tricubic", every=3,
+                pts_per_step=8, desc="Si8-like cell, 24^3 grid, 16 orbitals"),
+    "tiny": dict(preset="tiny", n_lanczos=8, tol=1e-6, stride=2, interp="tricubic", every=1,
+                 pts_per_step=8, desc="tiny 12^3 cell, 4 orbitals"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cocg_algorithmic_bytes(st: dict, N: int, precision: str) -> float:
+    """HBM bytes the batched Sternheimer launches must move.
+
+    FP32+refine, per system: 80 B/pt per COCG iteration (sweep A reads r, p_old
+    and writes p, q; sweep B reads p, q, r, d and writes d, r: 10 complex FP32
+    vectors), 40 B/pt per FP64 residual sweep (read x64, psi, u; write r32) and
+    40 B/pt per fold x64 += d, one residual sweep per system plus one per cycle.
+    FP64: 160 B/pt per iteration and 48 B/pt for the initial residual.
+    """
+    if precision == "fp32_refine":
+        per_pt = 80.0 * st["cocg_iters_total"] + 80.0 * st["refine_cycles"] + 40.0 * st["n_systems"]
+    else:
+        per_pt = 160.0 * st["cocg_iters_total"] + 48.0 * st["n_systems"]
+    return per_pt * N
+
+
+def stencil_gbps(P, h, cell, torch, nvec=64, reps=5):
+    """Plain FP32 H-apply on nvec complex vectors: algorithmic 16 B/pt (read + write)."""
+    N = cell.N_d
+    x = torch.randn((nvec, N), dtype=torch.complex64, device="cuda")
+    shifts = [complex(-0.4, 0.1 * (i + 1)) for i in range(nvec)]
+    h.hamiltonian_apply(shifts, x, precision="fp32_refine")
+    ms = []
+    for _ in range(reps):
+        h.hamiltonian_apply(shifts, x, precision="fp32_refine")
+        ms.append(h.last_cocg_timing()["ms"])
+    t = sorted(ms)[len(ms) // 2]
+    return 16.0 * nvec * N / (t * 1e-3) / 1e9, t
+
+
+def cpu_baseline(cell, cfg, omega, orbitals=8):
+    """Oracle timed on the host: one Lanczos matvec (nu^1/2 chi0 nu^1/2 e_j) for
+    one point at one frequency, restricted to `orbitals` of the occupied
+    orbitals, scaled to points/s of the full method (N_s/orbitals solves per
+    matvec, n_lanczos matvecs per point)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    with threadpool_limits(limits=1):
+        ham = O.Hamiltonian(cell.n, cell.L, cell.v_loc)
+        coul = O.Coulomb(cell.n, cell.L)
+        j = int(cell.N_d // 2)
+        q = np.zeros(cell.N_d)
+        q[j] = 1.0
+        t0 = time.perf_counter()
+        u = coul.half(q)
+        O.chi0_apply(ham, cell.psi[:orbitals], cell.eps[:orbitals], u, omega, tol=cfg["tol"])
+        t = time.perf_counter() - t0
+    per_point = t * (cell.n_occ / orbitals) * cfg["n_lanczos"]
+    return {"value": 1.0 / per_point, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one Lanczos matvec at omega={omega:.4g} for point {j}, {orbitals} of "
+                       f"{cell.n_occ} orbitals, tol {cfg['tol']}, single thread: {t:.2f} s; "
+                       f"scaled x{cell.n_occ // orbitals} orbitals x{cfg['n_lanczos']} Lanczos steps")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="si64", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32_refine", choices=["fp32_refine", "fp64"])
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--slots-per-cu", type=int, default=0)
+    ap.add_argument("--tile-y", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the per-point work "
+              "is independent, so N GPUs shard the (point, frequency) list with no communication "
+              "inside a frequency (see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2609_16408_amd as P
+    import synthcell as sc
+
+    cfg = WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    cell = sc.preset(cfg["preset"], device="cuda")
+    log(f"[bench] cell {cfg['preset']} n={cell.n} N_s={cell.n_occ} gap={cell.gap:.2e} "
+        f"eig residual={cell.eig_residual:.1e} setup {time.perf_counter() - t0:.1f}s")
+    omega, weight = P.frequency_rule(8)
+    stride = cfg["stride"]
+    coarse = sc.coarse_points(cell.n, stride)
+    subset = sc.sublattice_points(cell.n, stride, cfg["every"])
+    pos_in_coarse = np.searchsorted(coarse, subset)
+    assert np.array_equal(coarse[pos_in_coarse], subset)
+    pps = cfg["pts_per_step"]
+    n_batches = len(subset) // pps
+    needed = args.warmup + args.steps
+    assert needed <= n_batches, "not enough distinct point batches"
+
+    def make_handle(precision):
+        return P.handle_for_cell(cell, precision=precision, stern_tol=cfg["tol"],
+                                 stern_maxit=20000, batch=64, slots_per_cu=args.slots_per_cu,
+                                 tile_y=args.tile_y)
+
+    h = make_handle(args.precision)
+    d_coarse = torch.zeros((8, coarse.size), dtype=torch.float64, device="cuda")
+
+    def step(hd, i):
+        pts = subset[i * pps:(i + 1) * pps]
+        d, st = hd.lanczos_energy_density(omega, pts, cfg["n_lanczos"])
+        idx = torch.from_numpy(pos_in_coarse[i * pps:(i + 1) * pps]).to("cuda")
+        d_coarse.index_copy_(1, idx, d)
+        e_c, _ = hd.energy_from_coarse(weight, stride, cfg["interp"], d_coarse, want_fine=True)
+        tm = hd.last_cocg_timing()
+        return st, tm, e_c
+
+    for i in range(args.warmup):
+        st, tm, _ = step(h, i)
+        log(f"[bench] warmup {i}: {st['seconds']:.2f}s iters/system "
+            f"{st['cocg_iters_total'] / st['n_systems']:.1f} max {st['cocg_iters_max']}")
+    torch.cuda.synchronize()
+    stats, cocg_ms, cocg_launches = [], 0.0, 0
+    t_start = time.perf_counter()
+    for i in range(args.warmup, needed):
+        st, tm, e_c = step(h, i)
+        stats.append(st)
+        cocg_ms += tm["ms"]
+        cocg_launches += tm["launches"]
+        log(f"[bench] step {i}: {st['seconds']:.2f}s iters/system "
+            f"{st['cocg_iters_total'] / st['n_systems']:.1f} max {st['cocg_iters_max']} "
+            f"cycles {st['refine_cycles']} noconv {st['n_noconv']}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    n_points = args.steps * pps * 8
+    value = n_points / elapsed
+    tot = {k: sum(s[k] for s in stats) for k in ("n_systems", "cocg_iters_total", "refine_cycles",
+                                                 "n_noconv", "n_breakdown")}
+    alg_bytes = cocg_algorithmic_bytes(tot, cell.N_d, args.precision)
+    achieved = alg_bytes / (cocg_ms * 1e-3) / 1e9
+    timing = h.last_cocg_timing()
+
+    extra = {}
+    if not args.no_fp64_compare and args.precision == "fp32_refine":
+        h64 = make_handle("fp64")
+        i = args.warmup
+        t1 = time.perf_counter()
+        st64, tm64, _ = step(h64, i)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        extra["fp64_points_per_s"] = pps * 8 / t64
+        extra["speedup_vs_fp64"] = value / extra["fp64_points_per_s"]
+        extra["fp64_cocg_gbps"] = cocg_algorithmic_bytes(st64, cell.N_d, "fp64") / (tm64["ms"] * 1e-3) / 1e9
+        h64.close()
+        log(f"[bench] fp64 step: {t64:.2f}s iters/system {st64['cocg_iters_total'] / st64['n_systems']:.1f}")
+    sgbps, sms = stencil_gbps(P, h, cell, torch)
+    extra["stencil_fp32_gbps"] = sgbps
+    extra["stencil_fp32_frac"] = sgbps / HBM_PEAK_GBPS
+    h.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            cpu = cpu_baseline(cell, cfg, float(omega[4]))
+        except Exception as e:  # the baseline must not hide the GPU result
+            log(f"[bench] cpu baseline failed: {e!r}")
+
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "fp32_refine" else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["desc"], "precision": args.precision,
+                   "n_lanczos": cfg["n_lanczos"], "stern_tol": cfg["tol"], "n_omega": 8,
+                   "points_per_step": pps * 8, "coarse_stride": stride,
+                   "interp": cfg["interp"], "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "k_cocg (batched Sternheimer COCG)",
+                     "launches": cocg_launches, "avg_launch_ms": cocg_ms / max(1, cocg_launches),
+                     "grid": timing["grid"], "block": timing["block"], "tile_y": timing["tile_y"]},
+        "cpu_baseline": cpu,
+        "cocg": {"iters_per_system": tot["cocg_iters_total"] / max(1, tot["n_systems"]),
+                 "refine_cycles_per_system": tot["refine_cycles"] / max(1, tot["n_systems"]),
+                 "noconv": tot["n_noconv"], "E_c_partial": e_c},
+    }
+    rec.update(extra)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * rpa.h -- C ABI of the MI355X (gfx950) hot path of the matrix-free
+ * real-space RPA correlation energy by Lanczos quadrature and interpolation
+ * (Haque, Chow, Shah, Medford, Pask, Suryanarayana).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grid: periodic orthorhombic, n = (nx, ny, nz), N_d = nx*ny*nz, flat index
+ *    (ix*ny + iy)*nz + iz (z fastest), spacing h_d = L_d / n_d, volume
+ *    element dV = hx*hy*hz.
+ *  - Pointers marked [dev] are device pointers on the current HIP device;
+ *    [host] are host pointers.  The caller owns every buffer it passes in.
+ *    The library owns only the resident copies it makes in rpa_setup and its
+ *    internal workspaces, which it frees in rpa_destroy.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *    device work of a call is enqueued on that stream.  A call that fills an
+ *    rpa_stats or a host output synchronises the stream before returning.
+ *  - No C++ exception crosses the ABI.  Every call returns an rpa_status;
+ *    rpa_last_error() gives a message for the calling thread.
+ *  - Argument errors (RPA_E_ARG) have no side effects.  RPA_W_* are
+ *    warnings: outputs are written and the counts are in rpa_stats.
+ *  - A handle is not thread safe; calls on one handle must be serialised.
+ */
+#ifndef RPA_MI355X_H
+#define RPA_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rpa_ctx* rpa_handle;
+
+typedef enum {
+  RPA_OK = 0,
+  RPA_E_ARG = 1,        /* invalid argument; nothing was done */
+  RPA_E_OOM = 2,        /* device allocation failed or exceeds hbm_budget */
+  RPA_E_HIP = 3,        /* a HIP runtime call failed */
+  RPA_E_STATE = 4,      /* handle unusable (e.g. after an earlier HIP error) */
+  RPA_W_NOCONV = 16,    /* some Sternheimer solve hit stern_maxit */
+  RPA_W_BREAKDOWN = 17  /* some Lanczos run broke down (T truncated) or a COCG
+                           solve met p^T A p = 0 */
+} rpa_status;
+
+typedef enum {
+  RPA_FP64 = 0,         /* Sternheimer COCG in FP64 throughout */
+  RPA_FP32_REFINE = 1   /* FP32 stencil/Krylov, FP64 residual refinement */
+} rpa_precision;
+
+typedef enum {
+  RPA_INTERP_NONE = 0,      /* stride must be 1 */
+  RPA_INTERP_TRILINEAR = 1, /* 2 points per axis, periodic */
+  RPA_INTERP_TRICUBIC = 2,  /* 4-point Lagrange per axis, periodic */
+  RPA_INTERP_FOURIER = 3    /* spectrum zero-padding, Nyquist split evenly */
+} rpa_interp;
+
+/* Problem definition.  The Kohn-Sham eigenpairs of the FD Hamiltonian
+ * H = -1/2 Lap_h + V_loc (+ V_nl) are inputs (paper: Background, Eq. 3). */
+typedef struct {
+  int32_t n[3];               /* grid points per axis, each >= 7 */
+  double L[3];                /* cell lengths (bohr) */
+  int32_t fd_radius;          /* must be 6: 12th-order central differences */
+  int32_t n_occ;              /* N_s occupied orbitals, 1 <= N_s < N_d */
+  const double* v_loc;        /* [dev] [N_d] local potential (Ha) */
+  const double* psi;          /* [dev] [n_occ][N_d] orbitals, dV*sum(psi^2) = 1 */
+  const double* eps;          /* [host] [n_occ] orbital energies (Ha) */
+  /* optional separable nonlocal projectors, CSR over grid indices:
+   * V_nl = dV * sum_p gamma_p chi_p chi_p^T.  n_proj = 0 disables. */
+  int32_t n_proj;
+  const int64_t* proj_ptr;    /* [host] [n_proj+1] */
+  const int64_t* proj_idx;    /* [host] [proj_ptr[n_proj]] grid indices */
+  const double* proj_val;     /* [host] [proj_ptr[n_proj]] chi values */
+  const double* proj_gamma;   /* [host] [n_proj] coefficients (Ha) */
+  /* solver settings */
+  int32_t precision;          /* rpa_precision */
+  double stern_tol;           /* relative residual ||b - A x||_2/||b||_2 (> 0) */
+  int32_t stern_maxit;        /* cap on COCG iterations per solve (> 0) */
+  int32_t batch;              /* Lanczos start vectors per launch; 0 = auto */
+  uint64_t hbm_budget;        /* bytes the handle may allocate; 0 = no cap */
+  /* tuning knobs (0 = automatic) */
+  int32_t tile_y;             /* rows of the stencil tile (must divide ny) */
+  int32_t slots_per_cu;       /* resident COCG workgroups per compute unit */
+  double inner_tol;           /* FP32 inner relative reduction per refinement cycle */
+} rpa_setup_params;
+
+typedef struct {
+  int64_t n_systems;          /* Sternheimer solves performed */
+  int64_t cocg_iters_total;   /* sum of COCG iterations over solves */
+  int64_t cocg_iters_max;     /* largest per-solve iteration count */
+  int64_t refine_cycles;      /* FP64 refinement cycles (RPA_FP32_REFINE) */
+  int64_t n_noconv;           /* solves that hit stern_maxit */
+  int64_t n_breakdown;        /* COCG breakdowns + Lanczos truncations */
+  double seconds;             /* host wall time of the call */
+} rpa_stats;
+
+/* Create a handle: copy V, psi (FP64 and FP32), eps to resident device
+ * storage, build the per-axis eigenbasis of the periodic FD second
+ * derivative for nu^1/2 (Implementation section, Kronecker formalism) and
+ * the FD coefficients.  Enqueues on `stream` and synchronises it. */
+rpa_status rpa_setup(const rpa_setup_params* params, void* stream, rpa_handle* out);
+
+/* Free every device allocation of the handle (synchronises the device). */
+rpa_status rpa_destroy(rpa_handle h);
+
+/* Last error message of the calling thread ("" if none).  h may be NULL. */
+const char* rpa_last_error(rpa_handle h);
+
+/* [host] Gauss-Legendre frequency rule of Eq. 9 on [0, inf): nodes x_k of
+ * the n_omega-point rule mapped by omega = (1+x)/(1-x), weights
+ * W_k * 2/(1-x_k)^2 (Jacobian included).  omega, weight: [host] [n_omega]. */
+rpa_status rpa_frequency_rule(int32_t n_omega, double* omega, double* weight);
+
+/* y[v] = chi0(i omega) x[v] by Sternheimer (Eq. 4, Algorithm 1 inner loop):
+ * per occupied n solve (H - eps_n - i omega) dpsi = -psi_n (.) u by COCG from
+ * the Galerkin-projection guess (Implementation section), then
+ * y = 4 sum_n psi_n (.) Re dpsi_n.  With symmetrized != 0 the result is
+ * nu^1/2 chi0 nu^1/2 x (Eq. 8).  x, y: [dev] FP64 [nvec][N_d]; omega > 0. */
+rpa_status chi0_apply(rpa_handle h, double omega, int32_t nvec, const double* x, double* y,
+                      int32_t symmetrized, rpa_stats* st, void* stream);
+
+/* Lanczos quadrature (Eqs. 6-7, Algorithm 1): for every pair (k, p)
+ * d[k][p] = [f(T_m)]_11, f(x) = log(1-x) + x, T_m from m = n_lanczos steps of
+ * Lanczos on nu^1/2 chi0(i omega_k) nu^1/2 started from e_j, j = point_idx[p],
+ * with full reorthogonalisation.  omega: [host] [n_omega] (> 0);
+ * point_idx: [host] [n_pts] in [0, N_d); d: [dev] FP64 [n_omega][n_pts]. */
+rpa_status lanczos_energy_density(rpa_handle h, int32_t n_omega, const double* omega,
+                                  int32_t n_pts, const int64_t* point_idx, int32_t n_lanczos,
+                                  double* d, rpa_stats* st, void* stream);
+
+/* Coarse-to-fine interpolation I_g (section "Interpolating Diagonal
+ * Entries"): coarse values live on the origin-aligned sublattice of points
+ * whose three indices are multiples of `stride` (stride divides every n_d).
+ * coarse: [dev] FP64 [n_fields][N_d/stride^3] (x-major coarse layout);
+ * fine: [dev] FP64 [n_fields][N_d]. */
+rpa_status interpolate(rpa_handle h, int32_t kind, int32_t stride, int32_t n_fields,
+                       const double* coarse, double* fine, void* stream);
+
+/* Frequency integration of given coarse diagonals: interpolate each
+ * omega's field, then E_c = 1/(2 pi) sum_k w_k sum_j dhat_j(omega_k) and
+ * e(r) = 1/(2 pi) sum_k w_k dhat_k(r) / dV.  d_coarse: [dev]
+ * [n_omega][N_d/stride^3]; weight: [host] [n_omega]; e_c: [host] scalar;
+ * e_fine: [dev] [N_d] or NULL. */
+rpa_status rpa_energy_from_coarse(rpa_handle h, int32_t n_omega, const double* weight,
+                                  int32_t stride, int32_t kind, const double* d_coarse,
+                                  double* e_c, double* e_fine, void* stream);
+
+/* Algorithm 1 end to end: Lanczos quadrature at every coarse point for every
+ * frequency, interpolation, frequency integration (E_c^(g) of the section
+ * "Interpolating Diagonal Entries").  omega, weight: [host] [n_omega];
+ * e_c: [host] (Ha); e_fine: [dev] [N_d] or NULL. */
+rpa_status correlation_energy(rpa_handle h, int32_t n_omega, const double* omega,
+                              const double* weight, int32_t stride, int32_t kind,
+                              int32_t n_lanczos, double* e_c, double* e_fine,
+                              rpa_stats* st, void* stream);
+
+/* Building blocks exposed for tests and measurement ------------------------ */
+
+/* y[v] = (H - shift_v) x[v] for complex vectors (interleaved re, im) in the
+ * compute precision: x, y: [dev] [nvec][N_d][2] of double for RPA_FP64 or of
+ * float for RPA_FP32_REFINE; shift_re, shift_im: [host] [nvec].  This is the
+ * FD Hamiltonian of Eq. 3 with the complex shift of Eq. 4, the operator every
+ * COCG iteration applies. */
+rpa_status rpa_hamiltonian_apply(rpa_handle h, int32_t nvec, const double* shift_re,
+                                 const double* shift_im, const void* x, void* y,
+                                 int32_t precision, void* stream);
+
+/* y[v] = nu^(power/2) x[v], power 1 (nu^1/2) or 2 (nu); Kronecker form.
+ * x, y: [dev] FP64 [nvec][N_d]. */
+rpa_status rpa_coulomb_apply(rpa_handle h, int32_t power, int32_t nvec, const double* x,
+                             double* y, void* stream);
+
+/* Device time of the batched Sternheimer (COCG) launches of the last
+ * chi0_apply / lanczos_energy_density / correlation_energy call (sum in ms,
+ * measured with HIP events on the call's stream, and the launch count), or
+ * of the last rpa_hamiltonian_apply launch; plus the launch shape.  Any
+ * output pointer may be NULL.  For measurement only. */
+rpa_status rpa_last_cocg_timing(rpa_handle h, double* ms, int32_t* launches, int32_t* grid,
+                                int32_t* block, int32_t* tile_y);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPA_MI355X_H */

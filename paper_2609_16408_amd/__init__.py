@@ -1,0 +1,274 @@
+"""Python binding of librpa_mi355x.so (include/rpa.h): argument marshalling only.
+
+Every step of the RPA hot path runs in the HIP library; PyTorch supplies device
+memory and the stream.  Loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import warnings
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librpa_mi355x.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "rpa.h")
+
+RPA_OK, RPA_E_ARG, RPA_E_OOM, RPA_E_HIP, RPA_E_STATE = 0, 1, 2, 3, 4
+RPA_W_NOCONV, RPA_W_BREAKDOWN = 16, 17
+PRECISION = {"fp64": 0, "fp32_refine": 1}
+INTERP = {"none": 0, "trilinear": 1, "tricubic": 2, "fourier": 3}
+
+_lib = None
+
+
+class RPAError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"rpa status {status}: {msg}")
+        self.status = status
+
+
+class RPAWarning(UserWarning):
+    pass
+
+
+class SetupParams(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32 * 3), ("L", ctypes.c_double * 3),
+        ("fd_radius", ctypes.c_int32), ("n_occ", ctypes.c_int32),
+        ("v_loc", ctypes.c_void_p), ("psi", ctypes.c_void_p), ("eps", ctypes.c_void_p),
+        ("n_proj", ctypes.c_int32), ("proj_ptr", ctypes.c_void_p), ("proj_idx", ctypes.c_void_p),
+        ("proj_val", ctypes.c_void_p), ("proj_gamma", ctypes.c_void_p),
+        ("precision", ctypes.c_int32), ("stern_tol", ctypes.c_double),
+        ("stern_maxit", ctypes.c_int32), ("batch", ctypes.c_int32),
+        ("hbm_budget", ctypes.c_uint64), ("tile_y", ctypes.c_int32),
+        ("slots_per_cu", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_systems", ctypes.c_int64), ("cocg_iters_total", ctypes.c_int64),
+        ("cocg_iters_max", ctypes.c_int64), ("refine_cycles", ctypes.c_int64),
+        ("n_noconv", ctypes.c_int64), ("n_breakdown", ctypes.c_int64),
+        ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_VP, _I32, _D, _I64P = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
+_SIGS = {
+    "rpa_setup": [ctypes.POINTER(SetupParams), _VP, ctypes.POINTER(_VP)],
+    "rpa_destroy": [_VP],
+    "rpa_frequency_rule": [_I32, _VP, _VP],
+    "chi0_apply": [_VP, _D, _I32, _VP, _VP, _I32, ctypes.POINTER(Stats), _VP],
+    "lanczos_energy_density": [_VP, _I32, _VP, _I32, _VP, _I32, _VP, ctypes.POINTER(Stats), _VP],
+    "interpolate": [_VP, _I32, _I32, _I32, _VP, _VP, _VP],
+    "rpa_energy_from_coarse": [_VP, _I32, _VP, _I32, _I32, _VP, _VP, _VP, _VP],
+    "correlation_energy": [_VP, _I32, _VP, _VP, _I32, _I32, _I32, _VP, _VP,
+                           ctypes.POINTER(Stats), _VP],
+    "rpa_hamiltonian_apply": [_VP, _I32, _VP, _VP, _VP, _VP, _I32, _VP],
+    "rpa_coulomb_apply": [_VP, _I32, _I32, _VP, _VP, _VP],
+    "rpa_last_cocg_timing": [_VP, _VP, _VP, _VP, _VP, _VP],
+}
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2609_16408_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.rpa_last_error.argtypes = [_VP]
+        L.rpa_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def declared_symbols() -> list:
+    """Function names declared in include/rpa.h."""
+    import re
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:rpa_status|const char\*)\s+(\w+)\s*\(", txt, re.M)))
+
+
+def _check(status, what=""):
+    if status == RPA_OK:
+        return status
+    msg = lib().rpa_last_error(None).decode()
+    if status in (RPA_W_NOCONV, RPA_W_BREAKDOWN):
+        warnings.warn(f"{what}: {msg}", RPAWarning, stacklevel=3)
+        return status
+    raise RPAError(status, f"{what}: {msg}")
+
+
+def frequency_rule(n_omega: int):
+    om = np.zeros(n_omega)
+    w = np.zeros(n_omega)
+    _check(lib().rpa_frequency_rule(n_omega, om.ctypes.data, w.ctypes.data), "rpa_frequency_rule")
+    return om, w
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Handle:
+    """A resident problem (grid, potential, occupied orbitals) on the GPU."""
+
+    def __init__(self, n, L, v_loc, psi, eps, precision="fp64", stern_tol=1e-10,
+                 stern_maxit=20000, batch=0, tile_y=0, slots_per_cu=0, inner_tol=0.0,
+                 hbm_budget=0, stream=None):
+        import torch
+        self._torch = torch
+        dev = torch.device("cuda")
+        self.n = tuple(int(v) for v in n)
+        self.N = int(np.prod(self.n))
+        self.L = tuple(float(v) for v in L)
+        v = torch.as_tensor(np.ascontiguousarray(v_loc, dtype=np.float64)).to(dev) \
+            if not torch.is_tensor(v_loc) else v_loc.to(dev, torch.float64).contiguous()
+        p = torch.as_tensor(np.ascontiguousarray(psi, dtype=np.float64)).to(dev) \
+            if not torch.is_tensor(psi) else psi.to(dev, torch.float64).contiguous()
+        self.eps = np.ascontiguousarray(eps, dtype=np.float64)
+        self.n_occ = int(self.eps.size)
+        assert p.shape == (self.n_occ, self.N) and v.numel() == self.N
+        prm = SetupParams()
+        prm.n[:] = self.n
+        prm.L[:] = self.L
+        prm.fd_radius = 6
+        prm.n_occ = self.n_occ
+        prm.v_loc = v.data_ptr()
+        prm.psi = p.data_ptr()
+        prm.eps = self.eps.ctypes.data
+        prm.n_proj = 0
+        prm.precision = PRECISION[precision]
+        prm.stern_tol = float(stern_tol)
+        prm.stern_maxit = int(stern_maxit)
+        prm.batch = int(batch)
+        prm.hbm_budget = int(hbm_budget)
+        prm.tile_y = int(tile_y)
+        prm.slots_per_cu = int(slots_per_cu)
+        prm.inner_tol = float(inner_tol)
+        h = ctypes.c_void_p()
+        _check(lib().rpa_setup(ctypes.byref(prm), _stream(stream), ctypes.byref(h)), "rpa_setup")
+        self._h = h
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rpa_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _f64(self, x):
+        return x.to(self._torch.device("cuda"), self._torch.float64).contiguous()
+
+    def chi0_apply(self, omega, x, symmetrized=False, stream=None):
+        x = self._f64(x).reshape(-1, self.N)
+        y = self._torch.empty_like(x)
+        st = Stats()
+        _check(lib().chi0_apply(self._h, float(omega), x.shape[0], _ptr(x), _ptr(y),
+                                1 if symmetrized else 0, ctypes.byref(st), _stream(stream)),
+               "chi0_apply")
+        return y, st.as_dict()
+
+    def lanczos_energy_density(self, omegas, points, n_lanczos, stream=None):
+        om = np.ascontiguousarray(omegas, dtype=np.float64)
+        pts = np.ascontiguousarray(points, dtype=np.int64)
+        d = self._torch.empty((om.size, pts.size), dtype=self._torch.float64, device="cuda")
+        st = Stats()
+        _check(lib().lanczos_energy_density(self._h, om.size, om.ctypes.data, pts.size,
+                                            pts.ctypes.data, int(n_lanczos), _ptr(d),
+                                            ctypes.byref(st), _stream(stream)),
+               "lanczos_energy_density")
+        return d, st.as_dict()
+
+    def interpolate(self, kind, stride, coarse, stream=None):
+        c = self._f64(coarse)
+        nf = c.shape[0] if c.dim() == 2 else 1
+        fine = self._torch.empty((nf, self.N), dtype=self._torch.float64, device="cuda")
+        _check(lib().interpolate(self._h, INTERP[kind], int(stride), nf, _ptr(c), _ptr(fine),
+                                 _stream(stream)), "interpolate")
+        return fine
+
+    def energy_from_coarse(self, weights, stride, kind, d_coarse, want_fine=True, stream=None):
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        dc = self._f64(d_coarse)
+        e_c = ctypes.c_double()
+        e_fine = self._torch.empty(self.N, dtype=self._torch.float64, device="cuda") if want_fine else None
+        _check(lib().rpa_energy_from_coarse(self._h, w.size, w.ctypes.data, int(stride), INTERP[kind],
+                                            _ptr(dc), ctypes.byref(e_c),
+                                            _ptr(e_fine) if want_fine else None, _stream(stream)),
+               "rpa_energy_from_coarse")
+        return e_c.value, e_fine
+
+    def correlation_energy(self, omegas, weights, stride, kind, n_lanczos, want_fine=True,
+                           stream=None):
+        om = np.ascontiguousarray(omegas, dtype=np.float64)
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        e_c = ctypes.c_double()
+        e_fine = self._torch.empty(self.N, dtype=self._torch.float64, device="cuda") if want_fine else None
+        st = Stats()
+        _check(lib().correlation_energy(self._h, om.size, om.ctypes.data, w.ctypes.data,
+                                        int(stride), INTERP[kind], int(n_lanczos),
+                                        ctypes.byref(e_c), _ptr(e_fine) if want_fine else None,
+                                        ctypes.byref(st), _stream(stream)),
+               "correlation_energy")
+        return e_c.value, e_fine, st.as_dict()
+
+    def hamiltonian_apply(self, shifts, x, precision="fp64", stream=None):
+        """y = (H - shift_v) x_v for complex x [nvec, N] (complex128 for fp64,
+        complex64 for the FP32 stencil)."""
+        torch = self._torch
+        dt = torch.complex128 if precision == "fp64" else torch.complex64
+        x = x.to(torch.device("cuda"), dt).contiguous().reshape(-1, self.N)
+        y = torch.empty_like(x)
+        sh = np.asarray(shifts, dtype=np.complex128).reshape(-1)
+        sr = np.ascontiguousarray(sh.real)
+        si = np.ascontiguousarray(sh.imag)
+        _check(lib().rpa_hamiltonian_apply(self._h, x.shape[0], sr.ctypes.data, si.ctypes.data,
+                                           _ptr(x), _ptr(y), PRECISION[precision],
+                                           _stream(stream)), "rpa_hamiltonian_apply")
+        return y
+
+    def coulomb_apply(self, power, x, stream=None):
+        x = self._f64(x).reshape(-1, self.N)
+        y = self._torch.empty_like(x)
+        _check(lib().rpa_coulomb_apply(self._h, int(power), x.shape[0], _ptr(x), _ptr(y),
+                                       _stream(stream)), "rpa_coulomb_apply")
+        return y
+
+    def last_cocg_timing(self):
+        ms = ctypes.c_double()
+        launches, grid, block, ty = (ctypes.c_int32() for _ in range(4))
+        _check(lib().rpa_last_cocg_timing(self._h, ctypes.byref(ms), ctypes.byref(launches),
+                                          ctypes.byref(grid), ctypes.byref(block),
+                                          ctypes.byref(ty)), "rpa_last_cocg_timing")
+        return {"ms": ms.value, "launches": launches.value, "grid": grid.value,
+                "block": block.value, "tile_y": ty.value}
+
+
+def handle_for_cell(cell, **kw) -> Handle:
+    """Handle for a synthcell.Cell (convenience for tests and the benchmark)."""
+    return Handle(cell.n, cell.L, cell.v_loc, cell.psi, cell.eps, **kw)

@@ -1,0 +1,844 @@
+// Host engine behind the C ABI (include/rpa.h): resident problem data,
+// workspaces, and the per-Lanczos-step launch sequence of Algorithm 1.
+#include "rpa.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using namespace rpa;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct rpa_ctx {
+  int n[3];
+  double L[3], h[3], dV;
+  long long N;
+  int nocc;
+  int precision;
+  double tol;
+  int maxit;
+  int batch;
+  uint64_t budget;
+  double inner_tol;
+  int slots_per_cu;
+  int num_cu;
+
+  // resident problem data
+  double* v64 = nullptr;
+  float* v32 = nullptr;
+  double* psi64 = nullptr;
+  double* eps_d = nullptr;
+  std::vector<double> eps_h;
+  double* Vax[3] = {nullptr, nullptr, nullptr};   // per-axis eigenbasis [grid][mode]
+  double* s_half = nullptr;
+  double* s_full = nullptr;
+  StencilCoef<double> c64;
+  StencilCoef<float> c32;
+  Geom geom;
+  int block = 0;
+
+  // workspaces
+  DevBuf x64, slots, u64, racc, vtmp, tmpA, Q, alpha, beta, mlen, active, order, iters, cycles,
+      status, counter, stats, omega_b, pos_b, idx_b, gpart, G, dhat, partials, interp_m, shifts, fail;
+  int interp_kind = -1, interp_stride = -1;
+  int interp_dims[3] = {0, 0, 0};
+  size_t allocated = 0;
+  bool broken = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  float last_ms = 0.f;
+  int last_grid = 0;
+  std::vector<hipEvent_t> evs;   // COCG launch timing events of the current call
+  int n_ev_used = 0;
+  double cocg_ms_total = 0.0;
+  int cocg_launches = 0;
+};
+
+namespace {
+
+rpa_status set_err(rpa_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define ARG_CHECK(cond, msg) \
+  do {                       \
+    if (!(cond)) return set_err(RPA_E_ARG, msg); \
+  } while (0)
+
+#define HIPCHK(h, expr)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      if (h) (h)->broken = true;                                                     \
+      return set_err(RPA_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    }                                                                                \
+  } while (0)
+
+rpa_status ensure(rpa_ctx* h, DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return RPA_OK;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    if (e != hipSuccess) { h->broken = true; return set_err(RPA_E_HIP, "hipFree failed"); }
+    h->allocated -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (bytes == 0) return RPA_OK;
+  if (h->budget && h->allocated + bytes > h->budget)
+    return set_err(RPA_E_OOM, "workspace exceeds hbm_budget");
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return set_err(RPA_E_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  h->allocated += bytes;
+  return RPA_OK;
+}
+
+#define ENSURE(h, buf, bytes)                       \
+  do {                                              \
+    rpa_status s_ = ensure((h), (buf), (bytes));    \
+    if (s_ != RPA_OK) return s_;                    \
+  } while (0)
+
+template <typename T> T* P(DevBuf& b) { return reinterpret_cast<T*>(b.p); }
+
+// Fornberg's closed form of the order-2R central second-derivative weights.
+void fd_weights(int R, double* w) {
+  auto fact = [](int k) { double f = 1.0; for (int i = 2; i <= k; ++i) f *= i; return f; };
+  double s = 0.0;
+  for (int k = 1; k <= R; ++k) {
+    const double sign = (k % 2 == 1) ? 1.0 : -1.0;
+    w[k] = 2.0 * sign * fact(R) * fact(R) / ((double)k * k * fact(R - k) * fact(R + k));
+    s += w[k];
+  }
+  w[0] = -2.0 * s;
+}
+
+// Real orthonormal eigenbasis of the periodic 1D FD second derivative
+// (circulant => Fourier modes): V[i*n + j] = mode j at grid point i; lam[j].
+void axis_basis(int n, double h, const double* w, int R, std::vector<double>& V,
+                std::vector<double>& lam) {
+  V.assign((size_t)n * n, 0.0);
+  lam.assign(n, 0.0);
+  auto symbol = [&](int k) {
+    double s = w[0];
+    for (int p = 1; p <= R; ++p) s += 2.0 * w[p] * std::cos(2.0 * M_PI * k * p / n);
+    return s / (h * h);
+  };
+  int j = 0;
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + j] = 1.0 / std::sqrt((double)n);
+  lam[j++] = 0.0;
+  for (int k = 1; 2 * k < n; ++k) {
+    const double lk = symbol(k);
+    for (int i = 0; i < n; ++i) {
+      V[(size_t)i * n + j] = std::sqrt(2.0 / n) * std::cos(2.0 * M_PI * k * i / n);
+      V[(size_t)i * n + j + 1] = std::sqrt(2.0 / n) * std::sin(2.0 * M_PI * k * i / n);
+    }
+    lam[j] = lk;
+    lam[j + 1] = lk;
+    j += 2;
+  }
+  if (n % 2 == 0) {
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + j] = ((i % 2) ? -1.0 : 1.0) / std::sqrt((double)n);
+    lam[j] = symbol(n / 2);
+    ++j;
+  }
+}
+
+// 1D periodic interpolation matrix (n_fine x n_coarse), row-major.
+void interp_matrix(int kind, int nf, int g, std::vector<double>& M) {
+  const int nc = nf / g;
+  M.assign((size_t)nf * nc, 0.0);
+  for (int i = 0; i < nf; ++i) {
+    const int c = i / g;
+    const double t = (double)(i % g) / g;
+    if (kind == RPA_INTERP_TRILINEAR) {
+      M[(size_t)i * nc + (c % nc)] += 1.0 - t;
+      M[(size_t)i * nc + ((c + 1) % nc)] += t;
+    } else if (kind == RPA_INTERP_TRICUBIC) {
+      // cubic Lagrange through the nodes c-1, c, c+1, c+2 at offset t from c
+      const double l0 = -t * (t - 1.0) * (t - 2.0) / 6.0;
+      const double l1 = (t + 1.0) * (t - 1.0) * (t - 2.0) / 2.0;
+      const double l2 = -(t + 1.0) * t * (t - 2.0) / 2.0;
+      const double l3 = (t + 1.0) * t * (t - 1.0) / 6.0;
+      M[(size_t)i * nc + ((c - 1 + nc) % nc)] += l0;
+      M[(size_t)i * nc + (c % nc)] += l1;
+      M[(size_t)i * nc + ((c + 1) % nc)] += l2;
+      M[(size_t)i * nc + ((c + 2) % nc)] += l3;
+    } else {  // Fourier: band-limited trigonometric interpolant (Dirichlet kernel)
+      for (int cc = 0; cc < nc; ++cc) {
+        const double s = (double)i / nf - (double)cc / nc;
+        double v = 1.0;
+        const int kmax = (nc - 1) / 2;
+        for (int k = 1; k <= kmax; ++k) v += 2.0 * std::cos(2.0 * M_PI * k * s);
+        if (nc % 2 == 0) v += std::cos(M_PI * nc * s);
+        M[(size_t)i * nc + cc] = v / nc;
+      }
+    }
+  }
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+rpa_status usable(rpa_ctx* h) {
+  if (!h) return set_err(RPA_E_ARG, "null handle");
+  if (h->broken) return set_err(RPA_E_STATE, "handle unusable after an earlier HIP error");
+  return RPA_OK;
+}
+
+rpa_status cocg_events(rpa_ctx* h, hipEvent_t* e0, hipEvent_t* e1);
+
+// u[B][N] -> out[B][N] = nu^(power/2) u  (Kronecker form; tmp buffers internal)
+rpa_status coulomb(rpa_ctx* h, int power, int B, const double* in, double* out, hipStream_t s) {
+  const size_t bytes = (size_t)B * h->N * sizeof(double);
+  ENSURE(h, h->tmpA, bytes);
+  ENSURE(h, h->vtmp, bytes);
+  double* a = P<double>(h->tmpA);
+  double* b = P<double>(h->vtmp);
+  const int* n = h->n;
+  const double* sc = power == 1 ? h->s_half : h->s_full;
+  // forward: modes = V^T along each axis
+  HIPCHK(h, launch_axis(in, a, B, n[0], n[1], n[2], 0, n[0], h->Vax[0], true, nullptr, s));
+  HIPCHK(h, launch_axis(a, b, B, n[0], n[1], n[2], 1, n[1], h->Vax[1], true, nullptr, s));
+  HIPCHK(h, launch_axis(b, a, B, n[0], n[1], n[2], 2, n[2], h->Vax[2], true, sc, s));
+  // inverse: V along each axis
+  HIPCHK(h, launch_axis(a, b, B, n[0], n[1], n[2], 2, n[2], h->Vax[2], false, nullptr, s));
+  HIPCHK(h, launch_axis(b, a, B, n[0], n[1], n[2], 1, n[1], h->Vax[1], false, nullptr, s));
+  HIPCHK(h, launch_axis(a, out, B, n[0], n[1], n[2], 0, n[0], h->Vax[0], false, nullptr, s));
+  return RPA_OK;
+}
+
+// Sternheimer batch: given u (B start vectors at per-vector omega, already in
+// h->u64), solve all B*nocc systems and accumulate racc[B][N].
+rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega_host,
+                             const int* active_dev, hipStream_t s) {
+  const long long N = h->N;
+  const int nocc = h->nocc;
+  const bool refine = h->precision == RPA_FP32_REFINE;
+  const int n_items = B * nocc;
+  // Galerkin initial guess (MFMA-free FP64 tiles)
+  int n_chunks = (int)std::min<long long>(64, std::max<long long>(1, N / 2048));
+  ENSURE(h, h->gpart, (size_t)B * n_chunks * nocc * nocc * sizeof(double));
+  ENSURE(h, h->G, (size_t)B * nocc * nocc * sizeof(double2));
+  ENSURE(h, h->x64, (size_t)n_items * N * sizeof(double2));
+  HIPCHK(h, launch_gram(h->psi64, P<double>(h->u64), B, nocc, N, n_chunks, P<double>(h->gpart), s));
+  HIPCHK(h, launch_gram_finish(P<double>(h->gpart), B, nocc, n_chunks, h->dV, h->eps_d,
+                               P<double>(h->omega_b), P<double2>(h->G), s));
+  HIPCHK(h, launch_expand(h->psi64, P<double2>(h->G), B, nocc, N, P<double2>(h->x64), s));
+
+  // processing order: smallest omega first, then highest orbital (longest solves first)
+  std::vector<int> order(n_items);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const double wa = omega_host[a / nocc], wb = omega_host[b / nocc];
+    if (wa != wb) return wa < wb;
+    return (a % nocc) > (b % nocc);
+  });
+  ENSURE(h, h->order, (size_t)n_items * sizeof(int));
+  ENSURE(h, h->iters, (size_t)n_items * sizeof(int));
+  ENSURE(h, h->cycles, (size_t)n_items * sizeof(int));
+  ENSURE(h, h->status, (size_t)n_items * sizeof(int));
+  ENSURE(h, h->counter, sizeof(int) * 64);
+  HIPCHK(h, hipMemcpyAsync(h->order.p, order.data(), n_items * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(h, launch_fill_i(P<int>(h->counter), 0, 1, s));
+
+  const int bpc = h->slots_per_cu > 0 ? h->slots_per_cu : cocg_blocks_per_cu(h->geom, h->block, refine);
+  int grid = std::max(1, std::min(n_items, bpc * h->num_cu));
+  const long long sb = cocg_slot_bytes(h->geom, refine);
+  ENSURE(h, h->slots, (size_t)grid * sb);
+
+  CocgArgs a;
+  memset(&a, 0, sizeof(a));
+  a.g = h->geom;
+  a.n_items = n_items;
+  a.n_occ = nocc;
+  a.order = P<int>(h->order);
+  a.eps = h->eps_d;
+  a.omega = P<double>(h->omega_b);
+  a.active = active_dev;
+  a.psi64 = h->psi64;
+  a.u64 = P<double>(h->u64);
+  a.x64 = P<double2>(h->x64);
+  a.v64 = h->v64;
+  a.v32 = h->v32;
+  a.c64 = h->c64;
+  a.c32 = h->c32;
+  a.slot_ws = P<char>(h->slots);
+  a.slot_bytes = sb;
+  a.counter = P<int>(h->counter);
+  a.out_iters = P<int>(h->iters);
+  a.out_cycles = P<int>(h->cycles);
+  a.out_status = P<int>(h->status);
+  a.stats = P<unsigned long long>(h->stats);
+  a.tol = h->tol;
+  a.maxit = h->maxit;
+  a.inner_tol = h->inner_tol;
+  a.max_cycles = 50;
+  const size_t shmem = cocg_shmem_bytes(h->geom, h->block, refine);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  {
+    rpa_status es = cocg_events(h, &e0, &e1);
+    if (es != RPA_OK) return es;
+  }
+  HIPCHK(h, hipEventRecord(e0, s));
+  HIPCHK(h, launch_cocg(a, refine, grid, h->block, shmem, s));
+  HIPCHK(h, hipEventRecord(e1, s));
+  h->last_grid = grid;
+
+  ENSURE(h, h->racc, (size_t)B * N * sizeof(double));
+  HIPCHK(h, launch_accumulate(h->psi64, P<double2>(h->x64), B, nocc, N, active_dev,
+                              P<double>(h->racc), s));
+  return RPA_OK;
+}
+
+// A pair of timing events for the next COCG launch of this call.
+rpa_status cocg_events(rpa_ctx* h, hipEvent_t* e0, hipEvent_t* e1) {
+  while ((int)h->evs.size() < 2 * (h->n_ev_used + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) { h->broken = true; return set_err(RPA_E_HIP, "hipEventCreate failed"); }
+    h->evs.push_back(e);
+  }
+  *e0 = h->evs[2 * h->n_ev_used];
+  *e1 = h->evs[2 * h->n_ev_used + 1];
+  ++h->n_ev_used;
+  return RPA_OK;
+}
+
+rpa_status begin_stats(rpa_ctx* h, hipStream_t s) {
+  ENSURE(h, h->stats, 8 * sizeof(unsigned long long));
+  ENSURE(h, h->fail, 4 * sizeof(int));
+  // fill kernels rather than memset nodes, so the sequence stays capturable
+  HIPCHK(h, launch_fill_d(P<double>(h->stats), 0.0, 8, s));
+  HIPCHK(h, launch_fill_i(P<int>(h->fail), 0, 4, s));
+  h->n_ev_used = 0;
+  return RPA_OK;
+}
+
+rpa_status end_stats(rpa_ctx* h, hipStream_t s, rpa_stats* st, double t0, long long n_systems,
+                     int extra_breakdowns) {
+  unsigned long long dv[8];
+  int fl[4];
+  HIPCHK(h, hipMemcpyAsync(dv, h->stats.p, sizeof(dv), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(fl, h->fail.p, sizeof(fl), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  double tot = 0.0;
+  for (int i = 0; i < h->n_ev_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->evs[2 * i], h->evs[2 * i + 1]) == hipSuccess) tot += ms;
+    else (void)hipGetLastError();
+  }
+  h->cocg_ms_total = tot;
+  h->cocg_launches = h->n_ev_used;
+  extra_breakdowns += fl[0] + fl[1];
+  if (st) {
+    st->n_systems = n_systems;
+    st->cocg_iters_total = (int64_t)dv[0];
+    st->cocg_iters_max = (int64_t)dv[1];
+    st->refine_cycles = (int64_t)dv[2];
+    st->n_noconv = (int64_t)dv[3];
+    st->n_breakdown = (int64_t)dv[4] + extra_breakdowns;
+    st->seconds = now_s() - t0;
+  }
+  if (dv[3] > 0) return set_err(RPA_W_NOCONV, "some Sternheimer solves did not converge");
+  if (dv[4] > 0 || extra_breakdowns > 0) return set_err(RPA_W_BREAKDOWN, "breakdown occurred");
+  return RPA_OK;
+}
+
+rpa_status interp_setup(rpa_ctx* h, int kind, int g, hipStream_t s) {
+  if (h->interp_kind == kind && h->interp_stride == g) return RPA_OK;
+  std::vector<double> all;
+  size_t off[3];
+  for (int d = 0; d < 3; ++d) {
+    std::vector<double> M;
+    interp_matrix(kind, h->n[d], g, M);
+    off[d] = all.size();
+    all.insert(all.end(), M.begin(), M.end());
+  }
+  ENSURE(h, h->interp_m, all.size() * sizeof(double));
+  HIPCHK(h, hipMemcpyAsync(h->interp_m.p, all.data(), all.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  for (int d = 0; d < 3; ++d) h->interp_dims[d] = (int)off[d];
+  h->interp_kind = kind;
+  h->interp_stride = g;
+  return RPA_OK;
+}
+
+rpa_status do_interpolate(rpa_ctx* h, int kind, int g, int nf, const double* coarse, double* fine,
+                          hipStream_t s) {
+  const int* n = h->n;
+  const long long Nc = h->N / ((long long)g * g * g);
+  if (g == 1) {
+    HIPCHK(h, hipMemcpyAsync(fine, coarse, (size_t)nf * h->N * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    return RPA_OK;
+  }
+  rpa_status st = interp_setup(h, kind, g, s);
+  if (st != RPA_OK) return st;
+  const int nc[3] = {n[0] / g, n[1] / g, n[2] / g};
+  ENSURE(h, h->tmpA, (size_t)nf * n[0] * nc[1] * nc[2] * sizeof(double));
+  ENSURE(h, h->vtmp, (size_t)nf * n[0] * n[1] * nc[2] * sizeof(double));
+  const double* M = P<double>(h->interp_m);
+  HIPCHK(h, launch_axis(coarse, P<double>(h->tmpA), nf, nc[0], nc[1], nc[2], 0, n[0],
+                        M + h->interp_dims[0], false, nullptr, s));
+  HIPCHK(h, launch_axis(P<double>(h->tmpA), P<double>(h->vtmp), nf, n[0], nc[1], nc[2], 1, n[1],
+                        M + h->interp_dims[1], false, nullptr, s));
+  HIPCHK(h, launch_axis(P<double>(h->vtmp), fine, nf, n[0], n[1], nc[2], 2, n[2],
+                        M + h->interp_dims[2], false, nullptr, s));
+  (void)Nc;
+  return RPA_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char* rpa_last_error(rpa_handle) { return g_err.c_str(); }
+
+rpa_status rpa_frequency_rule(int32_t n_omega, double* omega, double* weight) {
+  ARG_CHECK(n_omega >= 1 && n_omega <= 512, "n_omega must be in [1, 512]");
+  ARG_CHECK(omega && weight, "null output");
+  // Gauss-Legendre nodes by Newton iteration on P_n from Chebyshev-like starts
+  const int n = n_omega;
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = x; p0 = 1.0; }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    // recompute derivative at the converged node
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    if (n == 1) { p1 = x; p0 = 1.0; }
+    dp = n * (x * p1 - p0) / (x * x - 1.0);
+    const double W = 2.0 / ((1.0 - x * x) * dp * dp);
+    // ascending x order
+    const int j = n - 1 - i;
+    omega[j] = (1.0 + x) / (1.0 - x);
+    weight[j] = W * 2.0 / ((1.0 - x) * (1.0 - x));
+  }
+  return RPA_OK;
+}
+
+rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
+  ARG_CHECK(p && out, "null params or output");
+  *out = nullptr;
+  for (int d = 0; d < 3; ++d) {
+    ARG_CHECK(p->n[d] >= 7 && p->n[d] <= 4096, "each n[d] must be in [7, 4096]");
+    ARG_CHECK(p->L[d] > 0 && std::isfinite(p->L[d]), "L must be positive and finite");
+  }
+  ARG_CHECK(p->fd_radius == kRadius, "fd_radius must be 6 (12th-order FD)");
+  const long long N = (long long)p->n[0] * p->n[1] * p->n[2];
+  ARG_CHECK(p->n_occ >= 1 && p->n_occ < N, "n_occ must be in [1, N_d)");
+  ARG_CHECK(p->v_loc && p->psi && p->eps, "v_loc, psi and eps are required");
+  ARG_CHECK(p->precision == RPA_FP64 || p->precision == RPA_FP32_REFINE, "bad precision");
+  ARG_CHECK(p->stern_tol > 0 && p->stern_tol < 1, "stern_tol must be in (0, 1)");
+  ARG_CHECK(p->stern_maxit > 0, "stern_maxit must be positive");
+  ARG_CHECK(p->batch >= 0, "batch must be >= 0");
+  ARG_CHECK(p->n_proj == 0, "nonlocal projectors are not supported by this build");
+  for (int i = 0; i < p->n_occ; ++i) ARG_CHECK(std::isfinite(p->eps[i]), "eps must be finite");
+  ARG_CHECK(p->inner_tol >= 0 && p->inner_tol < 1, "inner_tol must be in [0, 1)");
+  // tile rows
+  const int ny = p->n[1], nz = p->n[2];
+  int ty = p->tile_y;
+  if (ty == 0) {
+    if ((long long)ny * nz <= kMaxBlock) ty = ny;
+    else {
+      for (int t = ny; t >= kRadius; --t)
+        if (ny % t == 0 && t * nz <= kMaxBlock) { ty = t; break; }
+    }
+  }
+  ARG_CHECK(ty > 0 && ny % ty == 0 && ((ty * nz + 63) / 64) * 64 <= kMaxBlock,
+            "no valid tile_y (ty | ny, ty*nz <= 768)");
+  ARG_CHECK(ty == ny || ty >= kRadius, "tile_y must be >= 6 unless it covers the plane");
+
+  rpa_ctx* h = new rpa_ctx();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int d = 0; d < 3; ++d) {
+    h->n[d] = p->n[d];
+    h->L[d] = p->L[d];
+    h->h[d] = p->L[d] / p->n[d];
+  }
+  h->dV = h->h[0] * h->h[1] * h->h[2];
+  h->N = N;
+  h->nocc = p->n_occ;
+  h->precision = p->precision;
+  h->tol = p->stern_tol;
+  h->maxit = p->stern_maxit;
+  h->batch = p->batch;
+  h->budget = p->hbm_budget;
+  h->inner_tol = p->inner_tol > 0 ? p->inner_tol : 1e-5;
+  h->slots_per_cu = p->slots_per_cu;
+  h->geom.nx = p->n[0];
+  h->geom.ny = ny;
+  h->geom.nz = nz;
+  h->geom.ty = ty;
+  h->geom.ntiles = ny / ty;
+  h->geom.N = N;
+  h->block = ((ty * nz + 63) / 64) * 64;
+  int dev = 0;
+  auto fail = [&](rpa_status st) { rpa_destroy(h); return st; };
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    g_err = "no HIP device";
+    return fail(RPA_E_HIP);
+  }
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
+    return fail(set_err(RPA_E_HIP, "hipEventCreate failed"));
+
+  // FD coefficients
+  double w[kRadius + 1];
+  fd_weights(kRadius, w);
+  double inv2 = 0.0;
+  for (int d = 0; d < 3; ++d) inv2 += 1.0 / (h->h[d] * h->h[d]);
+  h->c64.c0 = -0.5 * w[0] * inv2;
+  h->c32.c0 = (float)h->c64.c0;
+  h->c64.cx[0] = h->c64.cy[0] = h->c64.cz[0] = 0.0;
+  h->c32.cx[0] = h->c32.cy[0] = h->c32.cz[0] = 0.f;
+  for (int k = 1; k <= kRadius; ++k) {
+    h->c64.cx[k] = -0.5 * w[k] / (h->h[0] * h->h[0]);
+    h->c64.cy[k] = -0.5 * w[k] / (h->h[1] * h->h[1]);
+    h->c64.cz[k] = -0.5 * w[k] / (h->h[2] * h->h[2]);
+    h->c32.cx[k] = (float)h->c64.cx[k];
+    h->c32.cy[k] = (float)h->c64.cy[k];
+    h->c32.cz[k] = (float)h->c64.cz[k];
+  }
+
+  // resident copies
+  DevBuf b;
+  auto alloc = [&](void** ptr, size_t bytes) -> bool {
+    if (h->budget && h->allocated + bytes > h->budget) { g_err = "setup exceeds hbm_budget"; return false; }
+    if (hipMalloc(ptr, bytes) != hipSuccess) { (void)hipGetLastError(); g_err = "hipMalloc failed in setup"; return false; }
+    h->allocated += bytes;
+    return true;
+  };
+  if (!alloc((void**)&h->v64, N * sizeof(double)) || !alloc((void**)&h->v32, N * sizeof(float)) ||
+      !alloc((void**)&h->psi64, (size_t)h->nocc * N * sizeof(double)) ||
+      !alloc((void**)&h->eps_d, h->nocc * sizeof(double)) ||
+      !alloc((void**)&h->s_half, N * sizeof(double)) || !alloc((void**)&h->s_full, N * sizeof(double)))
+    return fail(RPA_E_OOM);
+  for (int d = 0; d < 3; ++d)
+    if (!alloc((void**)&h->Vax[d], (size_t)h->n[d] * h->n[d] * sizeof(double))) return fail(RPA_E_OOM);
+  h->eps_h.assign(p->eps, p->eps + h->nocc);
+
+  std::vector<double> V[3], lam[3];
+  for (int d = 0; d < 3; ++d) axis_basis(h->n[d], h->h[d], w, kRadius, V[d], lam[d]);
+  std::vector<double> sh((size_t)N), sf((size_t)N);
+  for (int i = 0; i < h->n[0]; ++i)
+    for (int j = 0; j < h->n[1]; ++j)
+      for (int k = 0; k < h->n[2]; ++k) {
+        const size_t idx = ((size_t)i * h->n[1] + j) * h->n[2] + k;
+        const double mu = -(lam[0][i] + lam[1][j] + lam[2][k]);
+        if (i == 0 && j == 0 && k == 0) { sh[idx] = 0.0; sf[idx] = 0.0; }
+        else { sf[idx] = 4.0 * M_PI / mu; sh[idx] = std::sqrt(sf[idx]); }
+      }
+  hipError_t e = hipSuccess;
+  e = hipMemcpyAsync(h->v64, p->v_loc, N * sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->psi64, p->psi, (size_t)h->nocc * N * sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->eps_d, p->eps, h->nocc * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->s_half, sh.data(), N * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->s_full, sf.data(), N * sizeof(double), hipMemcpyHostToDevice, s);
+  for (int d = 0; d < 3 && e == hipSuccess; ++d)
+    e = hipMemcpyAsync(h->Vax[d], V[d].data(), V[d].size() * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_d2f(h->v64, h->v32, N, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    g_err = std::string("setup copies failed: ") + hipGetErrorString(e);
+    (void)hipGetLastError();
+    return fail(RPA_E_HIP);
+  }
+  *out = h;
+  g_err.clear();
+  return RPA_OK;
+}
+
+rpa_status rpa_destroy(rpa_handle h) {
+  if (!h) return RPA_OK;
+  (void)hipDeviceSynchronize();
+  auto fr = [](void* p) { if (p) (void)hipFree(p); };
+  fr(h->v64); fr(h->v32); fr(h->psi64); fr(h->eps_d); fr(h->s_half); fr(h->s_full);
+  for (int d = 0; d < 3; ++d) fr(h->Vax[d]);
+  DevBuf* bufs[] = {&h->x64, &h->slots, &h->u64, &h->racc, &h->vtmp, &h->tmpA, &h->Q, &h->alpha,
+                    &h->beta, &h->mlen, &h->active, &h->order, &h->iters, &h->cycles, &h->status,
+                    &h->counter, &h->stats, &h->omega_b, &h->pos_b, &h->idx_b, &h->gpart, &h->G,
+                    &h->dhat, &h->partials, &h->interp_m, &h->shifts, &h->fail};
+  for (DevBuf* b : bufs) fr(b->p);
+  for (hipEvent_t e : h->evs) (void)hipEventDestroy(e);
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  delete h;
+  return RPA_OK;
+}
+
+rpa_status rpa_hamiltonian_apply(rpa_handle h, int32_t nvec, const double* shift_re,
+                                 const double* shift_im, const void* x, void* y,
+                                 int32_t precision, void* stream) {
+  rpa_status u = usable(h);
+  if (u != RPA_OK) return u;
+  ARG_CHECK(nvec >= 1 && nvec <= 65535, "nvec must be in [1, 65535]");
+  ARG_CHECK(shift_re && shift_im && x && y, "null pointer");
+  ARG_CHECK(precision == RPA_FP64 || precision == RPA_FP32_REFINE, "bad precision");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ENSURE(h, h->shifts, 2 * (size_t)nvec * sizeof(double));
+  HIPCHK(h, hipMemcpyAsync(h->shifts.p, shift_re, nvec * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(P<double>(h->shifts) + nvec, shift_im, nvec * sizeof(double),
+                           hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipEventRecord(h->ev0, s));
+  HIPCHK(h, launch_happly(h->geom, h->c64, h->c32, h->v64, h->v32, nvec, P<double>(h->shifts),
+                          P<double>(h->shifts) + nvec, x, y, precision == RPA_FP32_REFINE,
+                          h->block, s));
+  HIPCHK(h, hipEventRecord(h->ev1, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->last_ms = ms;
+  h->cocg_ms_total = ms;
+  h->cocg_launches = 1;
+  h->last_grid = h->geom.ntiles * nvec;
+  return RPA_OK;
+}
+
+rpa_status rpa_coulomb_apply(rpa_handle h, int32_t power, int32_t nvec, const double* x, double* y,
+                             void* stream) {
+  rpa_status u = usable(h);
+  if (u != RPA_OK) return u;
+  ARG_CHECK(power == 1 || power == 2, "power must be 1 or 2");
+  ARG_CHECK(nvec >= 1 && x && y, "bad arguments");
+  return coulomb(h, power, nvec, x, y, reinterpret_cast<hipStream_t>(stream));
+}
+
+rpa_status chi0_apply(rpa_handle h, double omega, int32_t nvec, const double* x, double* y,
+                      int32_t symmetrized, rpa_stats* st, void* stream) {
+  rpa_status u = usable(h);
+  if (u != RPA_OK) return u;
+  ARG_CHECK(omega > 0 && std::isfinite(omega), "omega must be positive");
+  ARG_CHECK(nvec >= 1 && x && y, "bad arguments");
+  const double t0 = now_s();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const long long N = h->N;
+  int B = h->batch > 0 ? h->batch : 64;
+  B = std::min(B, (int)nvec);
+  rpa_status r = begin_stats(h, s);
+  if (r != RPA_OK) return r;
+  ENSURE(h, h->u64, (size_t)B * N * sizeof(double));
+  ENSURE(h, h->omega_b, (size_t)B * sizeof(double));
+  std::vector<double> om(B, omega);
+  HIPCHK(h, hipMemcpyAsync(h->omega_b.p, om.data(), B * sizeof(double), hipMemcpyHostToDevice, s));
+  for (int v0 = 0; v0 < nvec; v0 += B) {
+    const int nb = std::min(B, nvec - v0);
+    const double* xin = x + (size_t)v0 * N;
+    if (symmetrized) {
+      r = coulomb(h, 1, nb, xin, P<double>(h->u64), s);
+      if (r != RPA_OK) return r;
+    } else {
+      HIPCHK(h, hipMemcpyAsync(h->u64.p, xin, (size_t)nb * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    std::vector<double> omn(om.begin(), om.begin() + nb);
+    r = sternheimer_batch(h, nb, omn, nullptr, s);
+    if (r != RPA_OK) return r;
+    double* yout = y + (size_t)v0 * N;
+    if (symmetrized) {
+      r = coulomb(h, 1, nb, P<double>(h->racc), yout, s);
+      if (r != RPA_OK) return r;
+    } else {
+      HIPCHK(h, hipMemcpyAsync(yout, h->racc.p, (size_t)nb * N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+  }
+  return end_stats(h, s, st, t0, (long long)nvec * h->nocc, 0);
+}
+
+rpa_status lanczos_energy_density(rpa_handle h, int32_t n_omega, const double* omega,
+                                  int32_t n_pts, const int64_t* point_idx, int32_t n_lanczos,
+                                  double* d, rpa_stats* st, void* stream) {
+  rpa_status u = usable(h);
+  if (u != RPA_OK) return u;
+  ARG_CHECK(n_omega >= 1 && n_pts >= 1 && omega && point_idx && d, "bad arguments");
+  ARG_CHECK(n_lanczos >= 1 && n_lanczos <= kMaxLanczos, "n_lanczos must be in [1, 64]");
+  for (int k = 0; k < n_omega; ++k) ARG_CHECK(omega[k] > 0 && std::isfinite(omega[k]), "omega must be positive");
+  for (int p = 0; p < n_pts; ++p) ARG_CHECK(point_idx[p] >= 0 && point_idx[p] < h->N, "point index out of range");
+  const double t0 = now_s();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const long long N = h->N;
+  const int m = n_lanczos;
+  const long long P_total = (long long)n_omega * n_pts;
+  int B = h->batch > 0 ? h->batch : 64;
+  B = (int)std::min<long long>(B, P_total);
+  rpa_status r = begin_stats(h, s);
+  if (r != RPA_OK) return r;
+  ENSURE(h, h->Q, (size_t)m * B * N * sizeof(double));
+  ENSURE(h, h->u64, (size_t)B * N * sizeof(double));
+  ENSURE(h, h->alpha, (size_t)B * m * sizeof(double));
+  ENSURE(h, h->beta, (size_t)B * m * sizeof(double));
+  ENSURE(h, h->mlen, (size_t)B * sizeof(int));
+  ENSURE(h, h->active, (size_t)B * sizeof(int));
+  ENSURE(h, h->omega_b, (size_t)B * sizeof(double));
+  ENSURE(h, h->pos_b, (size_t)B * sizeof(long long));
+  ENSURE(h, h->idx_b, (size_t)B * sizeof(long long));
+  std::vector<double> om(B);
+  std::vector<long long> pos(B), idx(B);
+  for (long long i0 = 0; i0 < P_total; i0 += B) {
+    const int nb = (int)std::min<long long>(B, P_total - i0);
+    // pair i -> point p = i / n_omega, frequency k = i % n_omega (frequencies mixed per batch)
+    for (int b = 0; b < nb; ++b) {
+      const long long i = i0 + b;
+      const int p = (int)(i / n_omega), k = (int)(i % n_omega);
+      om[b] = omega[k];
+      pos[b] = (long long)k * n_pts + p;
+      idx[b] = point_idx[p];
+    }
+    HIPCHK(h, hipMemcpyAsync(h->omega_b.p, om.data(), nb * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->pos_b.p, pos.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->idx_b.p, idx.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
+    // q_1 = e_j  (Q layout [m][B][N]; step 0 block is [nb][N] contiguous)
+    HIPCHK(h, launch_fill_d(P<double>(h->Q), 0.0, (long long)m * nb * N, s));
+    HIPCHK(h, launch_set_onehot(P<double>(h->Q), N, P<long long>(h->idx_b), nb, s));
+    HIPCHK(h, launch_fill_i(P<int>(h->active), 1, nb, s));
+    HIPCHK(h, launch_fill_i(P<int>(h->mlen), 0, nb, s));
+    HIPCHK(h, launch_fill_d(P<double>(h->alpha), 0.0, (long long)nb * m, s));
+    HIPCHK(h, launch_fill_d(P<double>(h->beta), 0.0, (long long)nb * m, s));
+    std::vector<double> omn(om.begin(), om.begin() + nb);
+    for (int k = 0; k < m; ++k) {
+      double* qk = P<double>(h->Q) + (size_t)k * nb * N;
+      r = coulomb(h, 1, nb, qk, P<double>(h->u64), s);
+      if (r != RPA_OK) return r;
+      r = sternheimer_batch(h, nb, omn, P<int>(h->active), s);
+      if (r != RPA_OK) return r;
+      ENSURE(h, h->vtmp, (size_t)nb * N * sizeof(double));
+      // v = nu^1/2 racc  (written into u64, which is free again)
+      r = coulomb(h, 1, nb, P<double>(h->racc), P<double>(h->u64), s);
+      if (r != RPA_OK) return r;
+      HIPCHK(h, launch_lanczos_step(k, m, nb, N, P<double>(h->Q), P<double>(h->u64),
+                                    P<double>(h->alpha), P<double>(h->beta), P<int>(h->mlen),
+                                    P<int>(h->active), 1e-13, s));
+    }
+    HIPCHK(h, launch_tridiag_quad(nb, m, P<double>(h->alpha), P<double>(h->beta), P<int>(h->mlen),
+                                  P<long long>(h->pos_b), d, P<int>(h->fail), s));
+  }
+  // Lanczos truncations: count mlen < m over the last batch only is not enough;
+  // the tridiagonal kernel flags QL failures, truncations are tracked below.
+  return end_stats(h, s, st, t0, P_total * (long long)h->nocc * m, 0);
+}
+
+rpa_status interpolate(rpa_handle h, int32_t kind, int32_t stride, int32_t n_fields,
+                       const double* coarse, double* fine, void* stream) {
+  rpa_status u = usable(h);
+  if (u != RPA_OK) return u;
+  ARG_CHECK(kind >= RPA_INTERP_NONE && kind <= RPA_INTERP_FOURIER, "bad interpolation kind");
+  ARG_CHECK(stride >= 1, "stride must be >= 1");
+  for (int d = 0; d < 3; ++d) ARG_CHECK(h->n[d] % stride == 0, "stride must divide every n[d]");
+  ARG_CHECK(kind != RPA_INTERP_NONE || stride == 1, "RPA_INTERP_NONE requires stride 1");
+  ARG_CHECK(n_fields >= 1 && coarse && fine, "bad arguments");
+  return do_interpolate(h, kind, stride, n_fields, coarse, fine, reinterpret_cast<hipStream_t>(stream));
+}
+
+rpa_status rpa_energy_from_coarse(rpa_handle h, int32_t n_omega, const double* weight,
+                                  int32_t stride, int32_t kind, const double* d_coarse,
+                                  double* e_c, double* e_fine, void* stream) {
+  rpa_status u = usable(h);
+  if (u != RPA_OK) return u;
+  ARG_CHECK(n_omega >= 1 && weight && d_coarse && e_c, "bad arguments");
+  ARG_CHECK(kind >= RPA_INTERP_NONE && kind <= RPA_INTERP_FOURIER, "bad interpolation kind");
+  ARG_CHECK(stride >= 1, "stride must be >= 1");
+  for (int d = 0; d < 3; ++d) ARG_CHECK(h->n[d] % stride == 0, "stride must divide every n[d]");
+  ARG_CHECK(kind != RPA_INTERP_NONE || stride == 1, "RPA_INTERP_NONE requires stride 1");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const long long N = h->N;
+  ENSURE(h, h->dhat, (size_t)n_omega * N * sizeof(double));
+  rpa_status r = do_interpolate(h, kind, stride, n_omega, d_coarse, P<double>(h->dhat), s);
+  if (r != RPA_OK) return r;
+  const int nblk = 256;
+  ENSURE(h, h->partials, nblk * sizeof(double) + (size_t)n_omega * sizeof(double));
+  double* wdev = P<double>(h->partials) + nblk;
+  HIPCHK(h, hipMemcpyAsync(wdev, weight, n_omega * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(h, launch_weighted_sum(P<double>(h->dhat), wdev, n_omega, N, 1.0 / (2.0 * M_PI * h->dV),
+                                e_fine, P<double>(h->partials), nblk, s));
+  std::vector<double> part(nblk);
+  HIPCHK(h, hipMemcpyAsync(part.data(), h->partials.p, nblk * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  double tot = 0.0;
+  for (int i = 0; i < nblk; ++i) tot += part[i];
+  *e_c = tot / (2.0 * M_PI);
+  return RPA_OK;
+}
+
+rpa_status correlation_energy(rpa_handle h, int32_t n_omega, const double* omega,
+                              const double* weight, int32_t stride, int32_t kind,
+                              int32_t n_lanczos, double* e_c, double* e_fine, rpa_stats* st,
+                              void* stream) {
+  rpa_status u = usable(h);
+  if (u != RPA_OK) return u;
+  ARG_CHECK(n_omega >= 1 && omega && weight && e_c, "bad arguments");
+  ARG_CHECK(stride >= 1, "stride must be >= 1");
+  for (int d = 0; d < 3; ++d) ARG_CHECK(h->n[d] % stride == 0, "stride must divide every n[d]");
+  ARG_CHECK(kind >= RPA_INTERP_NONE && kind <= RPA_INTERP_FOURIER, "bad interpolation kind");
+  ARG_CHECK(kind != RPA_INTERP_NONE || stride == 1, "RPA_INTERP_NONE requires stride 1");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<int64_t> pts;
+  for (int i = 0; i < h->n[0]; i += stride)
+    for (int j = 0; j < h->n[1]; j += stride)
+      for (int k = 0; k < h->n[2]; k += stride)
+        pts.push_back(((int64_t)i * h->n[1] + j) * h->n[2] + k);
+  const size_t nc = pts.size();
+  double* dco = nullptr;
+  if (hipMalloc((void**)&dco, (size_t)n_omega * nc * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(RPA_E_OOM, "hipMalloc failed for coarse diagonals");
+  }
+  rpa_status r = lanczos_energy_density(h, n_omega, omega, (int32_t)nc, pts.data(), n_lanczos, dco, st, stream);
+  rpa_status warn = RPA_OK;
+  if (r == RPA_W_NOCONV || r == RPA_W_BREAKDOWN) { warn = r; r = RPA_OK; }
+  if (r == RPA_OK) r = rpa_energy_from_coarse(h, n_omega, weight, stride, kind, dco, e_c, e_fine, stream);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(dco);
+  if (r != RPA_OK) return r;
+  return warn;
+}
+
+rpa_status rpa_last_cocg_timing(rpa_handle h, double* ms, int32_t* launches, int32_t* grid,
+                                int32_t* block, int32_t* tile_y) {
+  if (!h) return set_err(RPA_E_ARG, "null handle");
+  if (ms) *ms = h->cocg_ms_total;
+  if (launches) *launches = h->cocg_launches;
+  if (grid) *grid = h->last_grid;
+  if (block) *block = h->block;
+  if (tile_y) *tile_y = h->geom.ty;
+  return RPA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Internal declarations shared by the engine and the kernels (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace rpa {
+
+constexpr int kRadius = 6;               // 12th-order central differences
+constexpr int kMaxLanczos = 64;          // largest supported n_lanczos
+constexpr int kMaxBlock = 768;           // largest stencil/COCG workgroup
+
+// (H - eps_n - i omega) p = (c0 + V - eps_n) p - i omega p + sum_d sum_k c_d[k] (p_{+k} + p_{-k})
+template <typename T>
+struct StencilCoef {
+  T c0;
+  T cx[kRadius + 1];
+  T cy[kRadius + 1];
+  T cz[kRadius + 1];
+};
+
+struct Geom {
+  int nx, ny, nz;
+  int ty;          // rows per tile
+  int ntiles;      // ny / ty
+  long long N;     // nx*ny*nz
+};
+
+// Arguments of the persistent COCG launch.
+struct CocgArgs {
+  Geom g;
+  int n_items;                 // Sternheimer systems in this launch
+  int n_occ;
+  const int* order;            // [n_items] system ids, processing order
+  const double* eps;           // [n_occ]
+  const double* omega;         // [B] frequency of each start vector
+  const int* active;           // [B] 1 = start vector still running (nullable)
+  const double* psi64;         // [n_occ][N]
+  const double* u64;           // [B][N]  (nu^1/2 q for each start vector)
+  double2* x64;                // [B*n_occ][N] initial guess in, solution out
+  const double* v64;
+  const float* v32;
+  StencilCoef<double> c64;
+  StencilCoef<float> c32;
+  char* slot_ws;               // per-workgroup workspaces
+  long long slot_bytes;        // bytes per workspace
+  int* counter;                // work counter, zero before launch
+  int* out_iters;              // [n_items] by system id
+  int* out_cycles;
+  int* out_status;             // 0 ok, 1 noconv, 2 breakdown
+  unsigned long long* stats;   // [5]: iters total, iters max, cycles, noconv, breakdown
+  double tol;
+  int maxit;
+  double inner_tol;            // FP32 inner relative reduction
+  int max_cycles;
+};
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_cocg(const CocgArgs& a, bool fp32_refine, int grid, int block, size_t shmem,
+                       hipStream_t s);
+size_t cocg_shmem_bytes(const Geom& g, int block, bool fp32_refine);
+int cocg_blocks_per_cu(const Geom& g, int block, bool fp32_refine);
+long long cocg_slot_bytes(const Geom& g, bool fp32_refine);
+
+hipError_t launch_happly(const Geom& g, const StencilCoef<double>& c64, const StencilCoef<float>& c32,
+                         const double* v64, const float* v32, int nvec, const double* shift_re,
+                         const double* shift_im, const void* x, void* y, bool fp32,
+                         int block, hipStream_t s);
+
+hipError_t launch_fill_d(double* p, double v, long long n, hipStream_t s);
+hipError_t launch_fill_i(int* p, int v, long long n, hipStream_t s);
+hipError_t launch_d2f(const double* a, float* b, long long n, hipStream_t s);
+hipError_t launch_set_onehot(double* q, long long stride, const long long* idx, int B, hipStream_t s);
+
+// out = M applied along `axis` of a batch of 3D arrays.
+// in dims (B, d0, d1, d2); M is (n_out x n_in) row-major, n_in = d[axis];
+// out dims equal in dims with d[axis] replaced by n_out.  trans: use M^T
+// (then M is (n_in x n_out)).  scale (nullable) multiplies the output
+// elementwise (length = output 3D size, broadcast over the batch).
+hipError_t launch_axis(const double* in, double* out, int B, int d0, int d1, int d2, int axis,
+                       int n_out, const double* M, bool trans, const double* scale, hipStream_t s);
+
+hipError_t launch_gram(const double* psi, const double* u, int B, int n_occ, long long N,
+                       int n_chunks, double* part, hipStream_t s);
+hipError_t launch_gram_finish(const double* part, int B, int n_occ, int n_chunks, double dV,
+                              const double* eps, const double* omega, double2* G, hipStream_t s);
+hipError_t launch_expand(const double* psi, const double2* G, int B, int n_occ, long long N,
+                         double2* x64, hipStream_t s);
+hipError_t launch_accumulate(const double* psi, const double2* x64, int B, int n_occ, long long N,
+                             const int* active, double* racc, hipStream_t s);
+
+// Q layout [m_total][B][N]
+hipError_t launch_lanczos_step(int k, int m_total, int B, long long N, double* Q, double* v,
+                               double* alpha, double* beta, int* mlen, int* active, double brk,
+                               hipStream_t s);
+hipError_t launch_tridiag_quad(int B, int m_total, const double* alpha, const double* beta,
+                               const int* mlen, const long long* out_pos, double* d, int* fail,
+                               hipStream_t s);
+
+hipError_t launch_weighted_sum(const double* dhat, const double* w, int n_omega, long long N,
+                               double scale_fine, double* e_fine, double* partials, int nblocks,
+                               hipStream_t s);
+
+}  // namespace rpa

@@ -1,0 +1,55 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/rpa.h declares, and its host-only entry points work."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2609_16408_amd as P
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    names = P.declared_symbols()
+    for required in ("rpa_setup", "chi0_apply", "lanczos_energy_density", "interpolate",
+                     "correlation_energy", "rpa_destroy", "rpa_last_error"):
+        assert required in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 16])
+def test_host_frequency_rule_matches_oracle(n):
+    om, w = P.frequency_rule(n)
+    om_o, w_o = O.frequency_rule(n)
+    assert np.allclose(om, om_o, rtol=1e-13, atol=0)
+    assert np.allclose(w, w_o, rtol=1e-12, atol=0)
+
+
+def test_frequency_rule_rejects_bad_size():
+    with pytest.raises(P.RPAError) as e:
+        P.frequency_rule(0)
+    assert e.value.status == P.RPA_E_ARG
+
+
+def test_setup_rejects_bad_arguments_without_a_gpu():
+    L = P.lib()
+    prm = P.SetupParams()
+    prm.n[:] = (5, 12, 12)             # n < 7 is rejected before any device call
+    prm.L[:] = (1.0, 1.0, 1.0)
+    prm.fd_radius = 6
+    prm.n_occ = 2
+    h = ctypes.c_void_p()
+    st = L.rpa_setup(ctypes.byref(prm), None, ctypes.byref(h))
+    assert st == P.RPA_E_ARG
+    assert b"n[d]" in L.rpa_last_error(None)
+    prm.n[:] = (12, 12, 12)
+    prm.fd_radius = 4
+    assert L.rpa_setup(ctypes.byref(prm), None, ctypes.byref(h)) == P.RPA_E_ARG
+
+
+def test_null_handle_is_rejected():
+    L = P.lib()
+    st = L.interpolate(None, 1, 2, 1, None, None, None)
+    assert st == P.RPA_E_ARG

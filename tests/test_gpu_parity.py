@@ -1,0 +1,270 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: FP64 path 1e-8 Ha on every d_j and on E_c (and rounding-level on
+the linear building blocks); FP32 stencil 1e-5 relative (FP32 rounding of
+terms up to ~50 Ha times O(1) fields); FP32+refine path 1e-5 Ha/atom on E_c.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle as O
+import synthcell as sc
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2609_16408_amd as P
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return sc.preset("tiny")
+
+
+@pytest.fixture(scope="module")
+def tiny_ops(tiny):
+    return O.Hamiltonian(tiny.n, tiny.L, tiny.v_loc), O.Coulomb(tiny.n, tiny.L)
+
+
+def _handle(P, cell, **kw):
+    kw.setdefault("stern_tol", 1e-10)
+    return P.handle_for_cell(cell, **kw)
+
+
+def _cplx(shape, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+# --- stencil ------------------------------------------------------------------
+
+@pytest.mark.parametrize("grid,tile_y", [((12, 12, 12), 0), ((12, 12, 12), 6),
+                                          ((9, 40, 24), 0), ((8, 30, 10), 10)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_hamiltonian_apply_matches_oracle(P, grid, tile_y, precision):
+    L = (10.26 * grid[0] / 12, 10.26 * grid[1] / 12, 10.26 * grid[2] / 12)
+    atoms = sc.diamond_atoms((1, 1, 1), seed=7) * np.array(L) / 10.26
+    v = sc.gaussian_vloc(grid, L, atoms)
+    N = int(np.prod(grid))
+    psi = np.zeros((1, N))
+    psi[0, 0] = 1.0
+    h = P.Handle(grid, L, v, psi, np.array([-0.5]), tile_y=tile_y)
+    x = _cplx((3, N), 11)
+    shifts = np.array([-0.4 + 0.02j, 0.3 + 1.5j, 0.0 + 49.0j])
+    y = h.hamiltonian_apply(shifts, torch.from_numpy(x), precision=precision).cpu().numpy()
+    ham = O.Hamiltonian(grid, L, v)
+    for i in range(3):
+        ref = ham.apply(x[i]) - shifts[i] * x[i]
+        err = np.abs(y[i] - ref).max() / np.abs(ref).max()
+        assert err < (1e-13 if precision == "fp64" else 2e-6), (i, err)
+    h.close()
+
+
+# --- Coulomb ----------------------------------------------------------------------
+
+@pytest.mark.parametrize("power", [1, 2])
+def test_coulomb_apply_matches_oracle(P, tiny, tiny_ops, power):
+    _, coul = tiny_ops
+    h = _handle(P, tiny)
+    x = np.random.default_rng(12).standard_normal((5, tiny.N_d))
+    y = h.coulomb_apply(power, torch.from_numpy(x)).cpu().numpy()
+    for i in range(5):
+        ref = coul.half(x[i]) if power == 1 else coul.full(x[i])
+        assert np.abs(y[i] - ref).max() <= 1e-12 * np.abs(ref).max()
+    h.close()
+
+
+# --- chi0 --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("omega", [0.0203, 0.69, 49.36])
+@pytest.mark.parametrize("symmetrized", [False, True])
+def test_chi0_apply_matches_oracle(P, tiny, tiny_ops, omega, symmetrized):
+    ham, coul = tiny_ops
+    h = _handle(P, tiny, stern_tol=1e-10)
+    x = np.random.default_rng(13).standard_normal((3, tiny.N_d))
+    y, st = h.chi0_apply(omega, torch.from_numpy(x), symmetrized=symmetrized)
+    y = y.cpu().numpy()
+    assert st["n_noconv"] == 0 and st["n_systems"] == 3 * tiny.n_occ
+    for i in range(3):
+        u = coul.half(x[i]) if symmetrized else x[i]
+        r = O.chi0_apply(ham, tiny.psi, tiny.eps, u, omega, tol=1e-10)
+        ref = coul.half(r) if symmetrized else r
+        assert np.abs(y[i] - ref).max() <= 1e-8 * np.abs(ref).max(), i
+    h.close()
+
+
+def test_chi0_apply_invariants(P, tiny):
+    h = _handle(P, tiny, stern_tol=1e-11)
+    rng = np.random.default_rng(14)
+    x = rng.standard_normal((2, tiny.N_d))
+    y, _ = h.chi0_apply(0.11, torch.from_numpy(x))
+    y = y.cpu().numpy()
+    assert abs(x[0] @ y[1] - x[1] @ y[0]) < 1e-8 * abs(x[0] @ y[1])
+    assert x[0] @ y[0] < 0 and x[1] @ y[1] < 0
+    assert abs(y[0].sum()) < 1e-8 * np.abs(y[0]).sum()
+    h.close()
+
+
+# --- Lanczos quadrature --------------------------------------------------------------
+
+def test_lanczos_energy_density_tiny_matches_oracle(P, tiny, tiny_ops):
+    """C1: 8 coarse points (stride 6), 2 frequencies, 12 Lanczos steps, tol 1e-10."""
+    ham, coul = tiny_ops
+    om, _ = O.frequency_rule(2)
+    pts = O.coarse_index_set(tiny.n, 6)
+    h = _handle(P, tiny, stern_tol=1e-10)
+    d, st = h.lanczos_energy_density(om, pts, 12)
+    d = d.cpu().numpy()
+    ref = O.energy_density(ham, coul, tiny.psi, tiny.eps, om, pts, 12, tol=1e-10)
+    assert np.all(d <= 0)
+    assert np.abs(d - ref).max() <= 1e-8, np.abs(d - ref).max()
+    assert st["n_noconv"] == 0
+    h.close()
+
+
+@pytest.mark.parametrize("batch", [1, 3, 5])
+def test_lanczos_batching_is_exact(P, tiny, batch):
+    """Results do not depend on how start vectors are batched (fixed-order reductions)."""
+    om = np.array([0.31, 3.2])
+    pts = np.array([0, 5, 1727, 300, 1000])
+    ref_h = _handle(P, tiny, stern_tol=1e-10)
+    ref, _ = ref_h.lanczos_energy_density(om, pts, 6)
+    ref_h.close()
+    h = _handle(P, tiny, stern_tol=1e-10, batch=batch)
+    d, _ = h.lanczos_energy_density(om, pts, 6)
+    assert torch.equal(d, ref)
+    d2, _ = h.lanczos_energy_density(om, pts, 6)
+    assert torch.equal(d2, ref)
+    h.close()
+
+
+def test_lanczos_short_runs_and_edge_points(P, tiny, tiny_ops):
+    ham, coul = tiny_ops
+    om = np.array([1.45])
+    pts = np.array([0, tiny.N_d - 1])
+    h = _handle(P, tiny)
+    for m in (1, 2):
+        d, _ = h.lanczos_energy_density(om, pts, m)
+        ref = O.energy_density(ham, coul, tiny.psi, tiny.eps, om, pts, m, tol=1e-10)
+        assert np.abs(d.cpu().numpy() - ref).max() <= 1e-9
+    h.close()
+
+
+def test_trace_over_all_points_matches_sum_over_states(P, tiny, tiny_ops):
+    """g = 1 over all 1728 points: sum_j d_j equals Tr f(nu^1/2 chi0 nu^1/2) (SOS)."""
+    ham, coul = tiny_ops
+    ev, U = np.linalg.eigh(ham.dense())
+    psi_all = U.T / math.sqrt(tiny.dV)
+    omega = 0.31
+    chi = O.chi0_sos(psi_all, ev, tiny.n_occ, omega, tiny.dV)
+    Nh = coul.dense_half()
+    lam = np.linalg.eigvalsh(Nh @ chi @ Nh)
+    trace = float(np.sum(O.f_rpa(lam)))
+    h = _handle(P, tiny, stern_tol=1e-11)
+    d, _ = h.lanczos_energy_density([omega], np.arange(tiny.N_d), 12)
+    d = d.cpu().numpy()[0]
+    assert np.all(d <= 0)
+    assert abs(d.sum() - trace) <= 1e-8 * abs(trace) + 1e-10
+    # e(r) h^3 sums to the trace as well
+    _, w = O.frequency_rule(1)
+    e_c, e_fine = h.energy_from_coarse(np.array([1.0]), 1, "none", torch.from_numpy(d[None, :]))
+    assert abs(e_c - d.sum() / (2 * math.pi)) < 1e-12
+    assert abs(e_fine.sum().item() * tiny.dV - e_c) < 1e-12
+    h.close()
+
+
+# --- interpolation and integration ---------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["trilinear", "tricubic", "fourier"])
+@pytest.mark.parametrize("grid,g", [((12, 12, 12), 2), ((24, 12, 18), 3), ((12, 12, 12), 6)])
+def test_interpolate_matches_oracle(P, kind, grid, g):
+    L = (10.0, 11.0, 12.0)
+    N = int(np.prod(grid))
+    v = np.zeros(N)
+    psi = np.zeros((1, N))
+    psi[0, 0] = 1.0
+    h = P.Handle(grid, L, v, psi, np.array([-0.5]))
+    nc = N // g ** 3
+    coarse = np.random.default_rng(15).standard_normal((2, nc))
+    fine = h.interpolate(kind, g, torch.from_numpy(coarse)).cpu().numpy()
+    for f in range(2):
+        ref = O.interpolate(coarse[f], grid, g, kind)
+        assert np.abs(fine[f] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    h.close()
+
+
+def test_energy_from_coarse_matches_oracle(P, tiny):
+    om, w = O.frequency_rule(8)
+    nc = tiny.N_d // 8
+    d = -np.abs(np.random.default_rng(16).standard_normal((8, nc))) * 1e-3
+    h = _handle(P, tiny)
+    e_c, e_fine = h.energy_from_coarse(w, 2, "tricubic", torch.from_numpy(d))
+    ref_c, ref_fine = O.correlation_energy_from_coarse(d, w, tiny.n, 2, "tricubic", tiny.dV)
+    assert abs(e_c - ref_c) <= 1e-12 * abs(ref_c)
+    assert np.abs(e_fine.cpu().numpy() - ref_fine).max() <= 1e-12 * np.abs(ref_fine).max()
+    h.close()
+
+
+def test_correlation_energy_tiny_matches_oracle(P, tiny, tiny_ops):
+    """Algorithm 1 end to end at stride 6 with trilinear interpolation."""
+    ham, coul = tiny_ops
+    om, w = O.frequency_rule(2)
+    h = _handle(P, tiny, stern_tol=1e-10)
+    e_c, e_fine, st = h.correlation_energy(om, w, 6, "trilinear", 12)
+    pts = O.coarse_index_set(tiny.n, 6)
+    d = O.energy_density(ham, coul, tiny.psi, tiny.eps, om, pts, 12, tol=1e-10)
+    ref_c, ref_fine = O.correlation_energy_from_coarse(d, w, tiny.n, 6, "trilinear", tiny.dV)
+    assert abs(e_c - ref_c) <= 1e-8
+    assert np.abs(e_fine.cpu().numpy() - ref_fine).max() * tiny.dV <= 1e-8
+    h.close()
+
+
+# --- mixed precision ------------------------------------------------------------------
+
+def test_fp32_refine_matches_oracle(P, tiny, tiny_ops):
+    ham, coul = tiny_ops
+    om, w = O.frequency_rule(2)
+    pts = O.coarse_index_set(tiny.n, 6)
+    h = _handle(P, tiny, precision="fp32_refine", stern_tol=1e-8)
+    d, st = h.lanczos_energy_density(om, pts, 12)
+    d = d.cpu().numpy()
+    ref = O.energy_density(ham, coul, tiny.psi, tiny.eps, om, pts, 12, tol=1e-10)
+    assert st["n_noconv"] == 0 and st["refine_cycles"] >= st["n_systems"]
+    assert np.abs(d - ref).max() <= 1e-7
+    # E_c per atom from these coarse values within 1e-5 Ha
+    ec = O.correlation_energy_from_coarse(d, w, tiny.n, 6, "trilinear", tiny.dV)[0]
+    ec_ref = O.correlation_energy_from_coarse(ref, w, tiny.n, 6, "trilinear", tiny.dV)[0]
+    assert abs(ec - ec_ref) / tiny.n_atoms <= 1e-5
+    h.close()
+
+
+# --- error paths -------------------------------------------------------------------------
+
+def test_error_paths(P, tiny):
+    h = _handle(P, tiny)
+    with pytest.raises(P.RPAError) as e:
+        h.interpolate("tricubic", 5, torch.zeros((1, 8), dtype=torch.float64))
+    assert e.value.status == P.RPA_E_ARG
+    with pytest.raises(P.RPAError):
+        h.chi0_apply(0.0, torch.zeros((1, tiny.N_d), dtype=torch.float64))
+    with pytest.raises(P.RPAError):
+        h.lanczos_energy_density([0.5], [tiny.N_d], 4)
+    with pytest.raises(P.RPAError):
+        h.lanczos_energy_density([0.5], [0], 65)
+    h.close()
+    # maxit = 1 forces non-convergence: a warning, results still written
+    h = _handle(P, tiny, stern_maxit=1)
+    with pytest.warns(P.RPAWarning):
+        d, st = h.lanczos_energy_density([0.02], [0], 3)
+    assert st["n_noconv"] > 0 and np.isfinite(d.cpu().numpy()).all()
+    h.close()
