@@ -81,14 +81,16 @@ typedef struct {
   /* tuning knobs (0 = automatic) */
   int32_t tile_y;             /* rows of the stencil tile (must divide ny) */
   int32_t slots_per_cu;       /* resident COCG workgroups per compute unit */
-  double inner_tol;           /* FP32 inner relative reduction per refinement cycle */
+  double inner_tol;           /* RPA_FP32_REFINE: the FP32 recursive residual is replaced
+                                 by the FP64 residual each time it drops by this
+                                 factor (reliable update); in (0, 1), 0 = 0.1 */
 } rpa_setup_params;
 
 typedef struct {
   int64_t n_systems;          /* Sternheimer solves performed */
   int64_t cocg_iters_total;   /* sum of COCG iterations over solves */
   int64_t cocg_iters_max;     /* largest per-solve iteration count */
-  int64_t refine_cycles;      /* FP64 refinement cycles (RPA_FP32_REFINE) */
+  int64_t refine_cycles;      /* FP64 residual replacements (RPA_FP32_REFINE) */
   int64_t n_noconv;           /* solves that hit stern_maxit */
   int64_t n_breakdown;        /* COCG breakdowns + Lanczos truncations */
   double seconds;             /* host wall time of the call */

@@ -18,10 +18,11 @@
 //    neighbouring planes and halo rows still need p_old); sweep B updates
 //    x, r and reduces r^T r and ||r||^2.  All reductions are per workgroup in
 //    a fixed order, so results do not depend on scheduling.
-//  * FP32_REFINE: inner COCG in FP32 on the residual system, FP64 residual
-//    r = b - A x recomputed by an FP64 stencil sweep after each cycle, the FP32
-//    correction folded into the FP64 solution.  b = -psi_n (.) u is formed on
-//    the fly in FP64 and never stored.
+//  * FP32_REFINE: COCG in FP32 with reliable updates: the FP32 correction is
+//    folded into the FP64 solution and the residual replaced by the FP64
+//    residual r = b - A x (an FP64 stencil sweep) whenever the recursive
+//    residual has dropped by a fixed factor; the search direction is kept.
+//    b = -psi_n (.) u is formed on the fly in FP64 and never stored.
 #include "internal.h"
 
 namespace rpa {
@@ -30,6 +31,7 @@ namespace {
 
 constexpr int R = kRadius;
 constexpr int QN = 2 * R + 1;
+constexpr int kMinGap = 4;   // fewest FP32 iterations between reliable updates
 
 template <typename T> struct V2;
 template <> struct V2<float> { typedef float2 t; };
@@ -89,13 +91,204 @@ __device__ __forceinline__ void block_reduce(double (&v)[K], double* red) {
 
 // ---------------------------------------------------------------------------
 // x-marching stencil sweep over all tiles of one system.
-// Pol provides:  T2 load(size_t off)  -- value of the operand at a point
-//                void center(size_t off, T2 val, T2 nbr)  -- nbr = sum of
-//                the off-centre stencil terms; the policy adds the diagonal.
-template <typename T, bool FULL, class Pol>
+//
+// Pol provides (po = uniform plane offset, c = per-lane offset in the plane):
+//   T2 load(size_t po, int c)  -- operand value at a point
+//   Aux aux(size_t po, int c)  -- centre-only data (potential, right-hand side)
+//   void center(size_t po, int c, T2 val, T2 nbr, const Aux&) -- nbr is the
+//   sum of the off-centre stencil terms.
+//
+// Each thread keeps planes x-R .. x+R+PF of its column in a register FIFO
+// whose slots rotate by compile-time phase (the x loop is unrolled by the
+// FIFO length U), so no register moves are needed; planes are loaded PF steps
+// before their first use.  The current plane sits in LDS with a compile-time
+// row pitch PITCH, padded with R periodic copies on each side in z (and in y
+// when one tile covers the whole plane), so all 24 in-plane neighbour reads
+// are immediate offsets from one per-thread base address.
+template <typename T> struct V2;
+
+template <typename T, bool FULL, int HS, int PITCH, class Pol>
+struct Marcher {
+  typedef typename V2<T>::t T2;
+  typedef typename Pol::Aux AuxT;
+  static constexpr int PF = Pol::kPF;
+  static constexpr int U = QN + PF;   // FIFO: planes x-R .. x+R+PF
+  static constexpr int PA = PF + 1;   // aux/halo pipelines: planes x .. x+PF
+  // The x loop is unrolled by U, so a slot index (phase within the block) of
+  // a pipeline of period PA equals x mod PA only if PA divides U
+  // (PF in {1, 2, 3, 5} for the 13-plane stencil).
+  static_assert(U % PA == 0, "prefetch depth must make PF+1 divide 2R+1+PF");
+
+  const Geom& g;
+  const StencilCoef<T>& cf;
+  Pol& pol;
+  T2* buf0;
+  T2* buf1;
+  size_t plane;
+  int nx;
+  bool own;
+  int col;            // own column offset in the plane (gy*nz + z)
+  int wbase;          // LDS index of the thread's stencil window (row rc-R, col z)
+  int ci;             // LDS index of the own point
+  int zpl, zpr;       // LDS indices of periodic copies in z (-1: none)
+  int ypl, ypr;       // ... and in y (whole-plane tiles only)
+  bool hv[HS];
+  int hl[HS];         // LDS index of halo points
+  int hcol[HS];       // halo column offsets in the plane
+  T2 fifo[U];
+  AuxT ax[PA];
+  T2 hq[HS][PA];
+
+  __device__ __forceinline__ static int wrapx(int p, int n) { return p >= n ? p - n : p; }
+
+  template <int PH>
+  __device__ __forceinline__ void step(int x) {
+    T2* buf = (x & 1) ? buf1 : buf0;
+    const T2 c = fifo[(PH + R) % U];
+    if (own) {
+      buf[ci] = c;
+      if (zpl >= 0) buf[zpl] = c;
+      if (zpr >= 0) buf[zpr] = c;
+      if (FULL) {
+        if (ypl >= 0) buf[ypl] = c;
+        if (ypr >= 0) buf[ypr] = c;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < HS; ++h)
+      if (hv[h]) buf[hl[h]] = hq[h][PH % PA];
+    __syncthreads();
+    if (own) {
+      const T2* w = buf + wbase;
+      T xr = 0, xi = 0, yr = 0, yi = 0, zr = 0, zi = 0;
+#pragma unroll
+      for (int k = 1; k <= R; ++k) {
+        const T2 a = fifo[(PH + R - k) % U];
+        const T2 b = fifo[(PH + R + k) % U];
+        xr += cf.w[k] * (a.x + b.x);
+        xi += cf.w[k] * (a.y + b.y);
+      }
+#pragma unroll
+      for (int k = 1; k <= R; ++k) {
+        const T2 a = w[(R - k) * PITCH + R];
+        const T2 b = w[(R + k) * PITCH + R];
+        yr += cf.w[k] * (a.x + b.x);
+        yi += cf.w[k] * (a.y + b.y);
+      }
+#pragma unroll
+      for (int k = 1; k <= R; ++k) {
+        const T2 a = w[R * PITCH + R - k];
+        const T2 b = w[R * PITCH + R + k];
+        zr += cf.w[k] * (a.x + b.x);
+        zi += cf.w[k] * (a.y + b.y);
+      }
+      const T sx = cf.sx * xr + cf.sy * yr + cf.sz * zr;
+      const T sy = cf.sx * xi + cf.sy * yi + cf.sz * zi;
+      pol.center((size_t)x * plane, col, c, mk2(sx, sy), ax[PH % PA]);
+    }
+    // refill the pipelines: the FIFO slot of plane x-R takes plane x+R+PF+1,
+    // the aux/halo slot of plane x takes plane x+PF+1
+    const int xn = x + PF + 1;
+    if (xn < nx) {
+      if (own) {
+        fifo[PH % U] = pol.load((size_t)wrapx(xn + R, nx) * plane, col);
+        ax[PH % PA] = pol.aux((size_t)xn * plane, col);
+      }
+#pragma unroll
+      for (int h = 0; h < HS; ++h)
+        if (hv[h]) hq[h][PH % PA] = pol.load((size_t)xn * plane, hcol[h]);
+    }
+  }
+
+  template <int PH>
+  __device__ __forceinline__ void block(int x) {
+    if constexpr (PH < U) {
+      if (x < nx) {
+        step<PH>(x);
+        block<PH + 1>(x + 1);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void run(int t_begin, int t_end) {
+    const int tid = threadIdx.x;
+    const int ny = g.ny, nz = g.nz, ty = g.ty;
+    own = tid < ty * nz;
+    const int ly = own ? tid / nz : 0;
+    const int z = own ? tid - ly * nz : 0;
+    const int nhalo = FULL ? 0 : 2 * R * nz;
+    int hrow[HS], hz[HS];
+#pragma unroll
+    for (int h = 0; h < HS; ++h) {
+      const int hid = tid + h * (int)blockDim.x;
+      hv[h] = hid < nhalo;
+      const int hr = hv[h] ? hid / nz : 0;
+      hz[h] = hv[h] ? hid - hr * nz : 0;
+      hrow[h] = hr;
+      hl[h] = (hr < R ? hr : ty + hr) * PITCH + hz[h] + R;
+    }
+    for (int t = t_begin; t < t_end; ++t) {
+      const int y0 = t * ty;
+      const int gy = y0 + ly;
+      col = gy * nz + z;
+      const int rc = (FULL ? gy : ly) + R;
+      ci = rc * PITCH + z + R;
+      wbase = (rc - R) * PITCH + z;
+      // a point is copied into the left pad if it is among the last R of the
+      // row and into the right pad if among the first R (both when nz < 2R)
+      zpl = z >= nz - R ? rc * PITCH + z + R - nz : -1;
+      zpr = z < R ? rc * PITCH + z + R + nz : -1;
+      ypl = -1;
+      ypr = -1;
+      if (FULL) {
+        ypl = gy >= ny - R ? (gy + R - ny) * PITCH + z + R : -1;
+        ypr = gy < R ? (gy + R + ny) * PITCH + z + R : -1;
+      }
+#pragma unroll
+      for (int h = 0; h < HS; ++h) {
+        int gr = hrow[h] < R ? y0 - R + hrow[h] : y0 + ty + (hrow[h] - R);
+        gr = gr < 0 ? gr + ny : (gr >= ny ? gr - ny : gr);
+        hcol[h] = gr * nz + hz[h];
+      }
+      // prologue: FIFO slot j holds plane j - R (phase 0); aux/halo slot j plane j
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const int px = ((j - R) % nx + nx) % nx;
+        fifo[j] = own ? pol.load((size_t)px * plane, col) : zero2<T2>();
+      }
+#pragma unroll
+      for (int j = 0; j < PA; ++j) {
+        ax[j] = own ? pol.aux((size_t)j * plane, col) : AuxT();
+#pragma unroll
+        for (int h = 0; h < HS; ++h)
+          hq[h][j] = hv[h] ? pol.load((size_t)j * plane, hcol[h]) : zero2<T2>();
+      }
+      for (int x = 0; x < nx; x += U) block<0>(x);
+      __syncthreads();
+    }
+  }
+};
+
+template <typename T, bool FULL, int HS, int PITCH, class Pol>
 __device__ __forceinline__ void march(const Geom& g, const StencilCoef<T>& cf, Pol& pol,
                                       typename V2<T>::t* lds, int t_begin, int t_end) {
+  const int rows = (FULL ? g.ny : g.ty) + 2 * R;
+  Marcher<T, FULL, HS, PITCH, Pol> m{g, cf, pol};
+  m.buf0 = lds;
+  m.buf1 = lds + rows * PITCH;
+  m.plane = (size_t)g.ny * g.nz;
+  m.nx = g.nx;
+  m.run(t_begin, t_end);
+}
+
+// Register-light variant for the occasional FP64 residual sweep: no x queue;
+// the 12 x neighbours are read through the caches (they were read moments
+// before by the neighbouring planes' steps), y/z neighbours from the LDS plane.
+template <typename T, bool FULL, int HS, class Pol>
+__device__ __forceinline__ void march_light(const Geom& g, const StencilCoef<T>& cf, Pol& pol,
+                                            typename V2<T>::t* lds, int t_begin, int t_end) {
   typedef typename V2<T>::t T2;
+  typedef typename Pol::Aux AuxT;
   const int tid = threadIdx.x;
   const int nx = g.nx, ny = g.ny, nz = g.nz, ty = g.ty;
   const int ncol = ty * nz;
@@ -104,17 +297,11 @@ __device__ __forceinline__ void march(const Geom& g, const StencilCoef<T>& cf, P
   const int z = own ? tid - ly * nz : 0;
   const int rows = FULL ? ny : ty + 2 * R;
   const size_t plane = (size_t)ny * nz;
-
-
-  // halo points (only when the tile does not cover the whole plane): each
-  // thread loads at most two of the 2R*nz halo values per plane (ty >= R).
   const int nhalo = FULL ? 0 : 2 * R * nz;
-  int hl[2];      // LDS element index
-  int hoff_r[2];  // halo row index in [0, 2R)
-  int hz[2];
-  bool hv[2];
+  int hl[HS], hoff_r[HS], hz[HS];
+  bool hv[HS];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < HS; ++j) {
     const int hid = tid + j * (int)blockDim.x;
     hv[j] = hid < nhalo;
     const int hr = hv[j] ? hid / nz : 0;
@@ -122,49 +309,39 @@ __device__ __forceinline__ void march(const Geom& g, const StencilCoef<T>& cf, P
     hoff_r[j] = hr;
     hl[j] = (hr < R ? hr : ty + hr) * nz + hz[j];
   }
-
   for (int t = t_begin; t < t_end; ++t) {
     const int y0 = t * ty;
     const int gy = y0 + ly;
     const size_t col = (size_t)gy * nz + z;
-    int hrowoff[2];
+    int hrowoff[HS];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < HS; ++j) {
       int gr = hoff_r[j] < R ? y0 - R + hoff_r[j] : y0 + ty + (hoff_r[j] - R);
       gr = gr < 0 ? gr + ny : (gr >= ny ? gr - ny : gr);
       hrowoff[j] = gr * nz + hz[j];
     }
-    // LDS row of the own point; y neighbours at rows rc +- k (wrapped when FULL)
     const int rc = FULL ? gy : ly + R;
-
-    T2 q[QN];
-#pragma unroll
-    for (int i = 0; i < QN; ++i) {
-      int px = i - R; px = px < 0 ? px + nx : (px >= nx ? px - nx : px);
-      q[i] = own ? pol.load(px * plane + col) : zero2<T2>();
-    }
-    int pn = R + 1; pn = pn >= nx ? pn - nx : pn;
-    T2 nxt = own ? pol.load(pn * plane + col) : zero2<T2>();
-    T2 hcur[2], hnxt[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      hcur[j] = hv[j] ? pol.load(hrowoff[j]) : zero2<T2>();
-      hnxt[j] = (hv[j] && nx > 1) ? pol.load(plane + hrowoff[j]) : zero2<T2>();
-    }
-
     for (int x = 0; x < nx; ++x) {
       T2* buf = lds + (x & 1) * rows * nz;
-      if (own) buf[rc * nz + z] = q[R];
+      const size_t po = (size_t)x * plane;
+      const T2 c = own ? pol.load(po, (int)col) : zero2<T2>();
+      if (own) buf[rc * nz + z] = c;
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        if (hv[j]) buf[hl[j]] = hcur[j];
+      for (int h = 0; h < HS; ++h)
+        if (hv[h]) buf[hl[h]] = pol.load(po, hrowoff[h]);
       __syncthreads();
       if (own) {
-        T ax = 0, ay = 0;
+        const AuxT axv = pol.aux(po, (int)col);
+        T xr = 0, xi = 0, yr = 0, yi = 0, zr = 0, zi = 0;
 #pragma unroll
         for (int k = 1; k <= R; ++k) {
-          ax += cf.cx[k] * (q[R - k].x + q[R + k].x);
-          ay += cf.cx[k] * (q[R - k].y + q[R + k].y);
+          int xp = x + k, xm = x - k;
+          xp -= xp >= nx ? nx : 0;
+          xm += xm < 0 ? nx : 0;
+          const T2 a = pol.load((size_t)xp * plane, (int)col);
+          const T2 b = pol.load((size_t)xm * plane, (int)col);
+          xr += cf.w[k] * (a.x + b.x);
+          xi += cf.w[k] * (a.y + b.y);
         }
 #pragma unroll
         for (int k = 1; k <= R; ++k) {
@@ -172,8 +349,8 @@ __device__ __forceinline__ void march(const Geom& g, const StencilCoef<T>& cf, P
           if (FULL) { up -= up >= ny ? ny : 0; dn += dn < 0 ? ny : 0; }
           const T2 a = buf[up * nz + z];
           const T2 b = buf[dn * nz + z];
-          ax += cf.cy[k] * (a.x + b.x);
-          ay += cf.cy[k] * (a.y + b.y);
+          yr += cf.w[k] * (a.x + b.x);
+          yi += cf.w[k] * (a.y + b.y);
         }
         const int rz = rc * nz;
 #pragma unroll
@@ -183,27 +360,28 @@ __device__ __forceinline__ void march(const Geom& g, const StencilCoef<T>& cf, P
           zm += zm < 0 ? nz : 0;
           const T2 a = buf[rz + zp];
           const T2 b = buf[rz + zm];
-          ax += cf.cz[k] * (a.x + b.x);
-          ay += cf.cz[k] * (a.y + b.y);
+          zr += cf.w[k] * (a.x + b.x);
+          zi += cf.w[k] * (a.y + b.y);
         }
-        pol.center(x * plane + col, q[R], mk2(ax, ay));
-      }
-#pragma unroll
-      for (int i = 0; i < QN - 1; ++i) q[i] = q[i + 1];
-      q[QN - 1] = nxt;
-      if (x + 1 < nx) {
-        int px = x + R + 2; px = px >= nx ? px - nx : px;
-        px = px >= nx ? px - nx : px;
-        if (own) nxt = pol.load(px * plane + col);
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        hcur[j] = hnxt[j];
-        if (hv[j] && x + 2 < nx) hnxt[j] = pol.load((size_t)(x + 2) * plane + hrowoff[j]);
+        const T sx = cf.sx * xr + cf.sy * yr + cf.sz * zr;
+        const T sy = cf.sx * xi + cf.sy * yi + cf.sz * zi;
+        pol.center(po, (int)col, c, mk2(sx, sy), axv);
       }
     }
     __syncthreads();
   }
+}
+
+// Bytes of LDS used by the plane buffers: the largest of the FIFO march (T of
+// the COCG iterations, padded pitch) and the FP64 light march (unpadded).
+__host__ __device__ inline size_t lds_plane_bytes(const Geom& g, int pitch, bool fp32_iter) {
+  const bool full = g.ty == g.ny;
+  const size_t rows_pad = (size_t)(full ? g.ny : g.ty) + 2 * R;
+  const size_t rows_light = full ? (size_t)g.ny : (size_t)g.ty + 2 * R;
+  const size_t main = 2 * rows_pad * pitch * (fp32_iter ? sizeof(float2) : sizeof(double2));
+  const size_t light = 2 * rows_light * g.nz * sizeof(double2);
+  const size_t b = main > light ? main : light;
+  return (b + 255) & ~(size_t)255;
 }
 
 // ---------------------------------------------------------------------------
@@ -220,16 +398,24 @@ struct ResidPol {
   TI2* r;
   double c0, eps, om;
   double rr, bb, rho_re, rho_im;
-  __device__ double2 load(size_t off) const { return x[off]; }
-  __device__ void center(size_t off, double2 xv, double2 nb) {
-    const double a = c0 + v[off] - eps;
+  static constexpr int kPF = 1;   // runs a few times per solve: keep registers low
+  struct Aux { double v, b; };
+  __device__ double2 load(size_t po, int c) const { return (x + po)[c]; }
+  __device__ Aux aux(size_t po, int c) const {
+    Aux a;
+    a.v = (v + po)[c];
+    a.b = -(psi + po)[c] * (u + po)[c];
+    return a;
+  }
+  __device__ void center(size_t po, int c, double2 xv, double2 nb, const Aux& ax) {
+    const double a = c0 + ax.v - eps;
     const double axr = a * xv.x + om * xv.y + nb.x;
     const double axi = a * xv.y - om * xv.x + nb.y;
-    const double bval = -psi[off] * u[off];
+    const double bval = ax.b;
     const double rx = bval - axr;
     const double ry = -axi;
     TI2 rs; rs.x = (TI)rx; rs.y = (TI)ry;
-    r[off] = rs;
+    (r + po)[c] = rs;
     rr += rx * rx + ry * ry;
     bb += bval * bval;
     const double sx = (double)rs.x, sy = (double)rs.y;
@@ -251,21 +437,24 @@ struct ApplyPol {
   T br, bi;
   bool first;
   double mu_re, mu_im;
-  __device__ T2 load(size_t off) const {
-    T2 rv = r[off];
+  static constexpr int kPF = sizeof(T) == 4 ? 3 : 2;
+  typedef T Aux;
+  __device__ T aux(size_t po, int c) const { return (v + po)[c]; }
+  __device__ T2 load(size_t po, int c) const {
+    T2 rv = (r + po)[c];
     if (first) return rv;
-    const T2 pv = pold[off];
+    const T2 pv = (pold + po)[c];
     rv.x += br * pv.x - bi * pv.y;
     rv.y += br * pv.y + bi * pv.x;
     return rv;
   }
-  __device__ void center(size_t off, T2 pv, T2 nb) {
-    const T a = c0 + v[off] - eps;
+  __device__ void center(size_t po, int c, T2 pv, T2 nb, const T& vv) {
+    const T a = c0 + vv - eps;
     T2 h;
     h.x = a * pv.x + om * pv.y + nb.x;
     h.y = a * pv.y - om * pv.x + nb.y;
-    pnew[off] = pv;
-    q[off] = h;
+    (pnew + po)[c] = pv;
+    (q + po)[c] = h;
     mu_re += (double)(pv.x * h.x - pv.y * h.y);
     mu_im += (double)(pv.x * h.y + pv.y * h.x);
   }
@@ -280,13 +469,16 @@ struct HPol {
   T2* y;
   const T* v;
   T c0, sr, si;
-  __device__ T2 load(size_t off) const { return x[off]; }
-  __device__ void center(size_t off, T2 xv, T2 nb) {
-    const T a = c0 + v[off] - sr;
+  static constexpr int kPF = sizeof(T) == 4 ? 3 : 2;
+  typedef T Aux;
+  __device__ T aux(size_t po, int c) const { return (v + po)[c]; }
+  __device__ T2 load(size_t po, int c) const { return (x + po)[c]; }
+  __device__ void center(size_t po, int c, T2 xv, T2 nb, const T& vv) {
+    const T a = c0 + vv - sr;
     T2 o;
     o.x = a * xv.x + si * xv.y + nb.x;
     o.y = a * xv.y - si * xv.x + nb.y;
-    y[off] = o;
+    (y + po)[c] = o;
   }
 };
 
@@ -294,6 +486,7 @@ struct HPol {
 // Streaming passes of one system (whole workgroup).
 
 // x (XT) = first ? alpha p : x + alpha p;  r -= alpha q;  returns ||r||^2, r^T r.
+// Four elements per thread per trip, all loads issued before the arithmetic.
 template <typename T, typename XT>
 __device__ __forceinline__ void update_sweep(long long N, typename V2<XT>::t* x,
                                              const typename V2<T>::t* p, typename V2<T>::t* r,
@@ -301,19 +494,46 @@ __device__ __forceinline__ void update_sweep(long long N, typename V2<XT>::t* x,
                                              double& rr, double& rho_re, double& rho_im) {
   typedef typename V2<T>::t T2;
   typedef typename V2<XT>::t X2;
-  for (long long i = threadIdx.x; i < N; i += blockDim.x) {
+  constexpr int U = 4;
+  const long long st = blockDim.x;
+  long long i0 = threadIdx.x;
+  for (; i0 + (U - 1) * st < N; i0 += U * st) {
+    T2 pv[U], qv[U], rv[U];
+    X2 xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long i = i0 + u * st;
+      pv[u] = p[i];
+      qv[u] = q[i];
+      rv[u] = r[i];
+      if (!first) xv[u] = x[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long i = i0 + u * st;
+      const T dx = ar * pv[u].x - ai * pv[u].y;
+      const T dy = ar * pv[u].y + ai * pv[u].x;
+      if (first) { xv[u].x = (XT)dx; xv[u].y = (XT)dy; }
+      else { xv[u].x += (XT)dx; xv[u].y += (XT)dy; }
+      x[i] = xv[u];
+      rv[u].x -= ar * qv[u].x - ai * qv[u].y;
+      rv[u].y -= ar * qv[u].y + ai * qv[u].x;
+      r[i] = rv[u];
+      const double sx = (double)rv[u].x, sy = (double)rv[u].y;
+      rr += sx * sx + sy * sy;
+      rho_re += sx * sx - sy * sy;
+      rho_im += 2.0 * sx * sy;
+    }
+  }
+  for (long long i = i0; i < N; i += st) {
     const T2 pv = p[i];
     const T2 qv = q[i];
     T2 rv = r[i];
     const T dx = ar * pv.x - ai * pv.y;
     const T dy = ar * pv.y + ai * pv.x;
     X2 xv;
-    if (first) {
-      xv.x = (XT)dx; xv.y = (XT)dy;
-    } else {
-      xv = x[i];
-      xv.x += (XT)dx; xv.y += (XT)dy;
-    }
+    if (first) { xv.x = (XT)dx; xv.y = (XT)dy; }
+    else { xv = x[i]; xv.x += (XT)dx; xv.y += (XT)dy; }
     x[i] = xv;
     rv.x -= ar * qv.x - ai * qv.y;
     rv.y -= ar * qv.y + ai * qv.x;
@@ -359,7 +579,7 @@ __device__ __forceinline__ void record(const CocgArgs& a, int s, int its, int cy
 
 // ---------------------------------------------------------------------------
 // One system, FP64 throughout.
-template <bool FULL>
+template <bool FULL, int HS, int PITCH>
 __device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red) {
   const Geom& g = a.g;
   const long long N = g.N;
@@ -379,7 +599,7 @@ __device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red) {
   rp.x = x; rp.v = a.v64; rp.psi = a.psi64 + (size_t)n * N; rp.u = a.u64 + (size_t)b * N;
   rp.r = r; rp.c0 = a.c64.c0; rp.eps = eps; rp.om = om;
   rp.rr = rp.bb = rp.rho_re = rp.rho_im = 0.0;
-  march<double, FULL>(g, a.c64, rp, lds, 0, g.ntiles);
+  march_light<double, FULL, HS>(g, a.c64, rp, lds, 0, g.ntiles);
   double v4[4] = {rp.rr, rp.bb, rp.rho_re, rp.rho_im};
   block_reduce<4>(v4, red);
   const double bnorm = sqrt(v4[1]);
@@ -400,7 +620,7 @@ __device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red) {
       ap.r = r; ap.pold = pold; ap.pnew = pnew; ap.q = q; ap.v = a.v64;
       ap.c0 = a.c64.c0; ap.eps = eps; ap.om = om; ap.br = br; ap.bi = bi; ap.first = first;
       ap.mu_re = ap.mu_im = 0.0;
-      march<double, FULL>(g, a.c64, ap, lds, 0, g.ntiles);
+      march<double, FULL, HS, PITCH>(g, a.c64, ap, lds, 0, g.ntiles);
       double m2[2] = {ap.mu_re, ap.mu_im};
       block_reduce<2>(m2, red);
       if (fabs(m2[0]) + fabs(m2[1]) < 1e-300) { status = 2; break; }
@@ -422,8 +642,13 @@ __device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red) {
   if (threadIdx.x == 0) record(a, s, its, 0, status);
 }
 
-// One system, FP32 inner COCG + FP64 residual refinement.
-template <bool FULL>
+// One system, FP32 COCG with reliable updates (Sleijpen and van der Vorst,
+// 1996): the search direction is kept for the whole solve, while every time
+// the FP32 recursive residual has dropped by the factor delta (inner_tol) the
+// FP32 correction d is folded into the FP64 solution and the residual is
+// replaced by the true FP64 residual b - A x64.  Convergence is declared on
+// the FP64 residual only.
+template <bool FULL, int HS, int PITCH>
 __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red) {
   const Geom& g = a.g;
   const long long N = g.N;
@@ -443,73 +668,91 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red) 
   rp.x = x; rp.v = a.v64; rp.psi = a.psi64 + (size_t)n * N; rp.u = a.u64 + (size_t)b * N;
   rp.r = r; rp.c0 = a.c64.c0; rp.eps = eps; rp.om = om;
   rp.rr = rp.bb = rp.rho_re = rp.rho_im = 0.0;
-  march<double, FULL>(g, a.c64, rp, reinterpret_cast<double2*>(smem), 0, g.ntiles);
+  march_light<double, FULL, HS>(g, a.c64, rp, reinterpret_cast<double2*>(smem), 0, g.ntiles);
   double v4[4] = {rp.rr, rp.bb, rp.rho_re, rp.rho_im};
   block_reduce<4>(v4, red);
   const double bnorm = sqrt(v4[1]);
-  double rnorm = sqrt(v4[0]);
+  double rnorm = sqrt(v4[0]);      // current residual estimate
   double rho_r = v4[2], rho_i = v4[3];
-  int its = 0, cycles = 0, status = 0;
+  int its = 0, updates = 0, status = 0;
   if (bnorm == 0.0) {
     zero_sweep(N, x);
   } else {
     const double thr = a.tol * bnorm;
+    const double delta = a.inner_tol;
+    double rmax = rnorm;           // true residual at the last update
+    double best_true = rnorm;      // smallest true residual seen
+    int no_gain = 0;               // updates in a row without progress
+    int last_upd = 0;              // iteration of the last update
+    double br = 0.0, bi = 0.0;
+    bool first = true;             // p = r (no previous direction)
+    bool dfresh = true;            // d holds nothing yet
+    float2* pold = pa;
+    float2* pnew = pb;
     while (rnorm > thr) {
-      if (its >= a.maxit || cycles >= a.max_cycles) { status = 1; break; }
-      // inner FP32 COCG on A d = r (d0 = 0): stop at ||r_in|| <= max(inner_tol*||r||, thr/2)
-      const double in_thr = fmax(a.inner_tol * rnorm, 0.5 * thr);
-      double br = 0.0, bi = 0.0;
-      bool first = true;
-      float2* pold = pa;
-      float2* pnew = pb;
-      double rin = rnorm;
-      bool broke = false;
-      while (rin > in_thr && its < a.maxit) {
-        ApplyPol<float> ap;
-        ap.r = r; ap.pold = pold; ap.pnew = pnew; ap.q = q; ap.v = a.v32;
-        ap.c0 = a.c32.c0; ap.eps = (float)eps; ap.om = (float)om; ap.br = (float)br;
-        ap.bi = (float)bi; ap.first = first;
-        ap.mu_re = ap.mu_im = 0.0;
-        march<float, FULL>(g, a.c32, ap, reinterpret_cast<float2*>(smem), 0, g.ntiles);
-        double m2[2] = {ap.mu_re, ap.mu_im};
-        block_reduce<2>(m2, red);
-        if (fabs(m2[0]) + fabs(m2[1]) < 1e-300) { broke = true; break; }
-        double al_r, al_i;
-        cdiv(rho_r, rho_i, m2[0], m2[1], al_r, al_i);
-        double rr = 0.0, nr = 0.0, ni = 0.0;
-        update_sweep<float, float>(N, d, pnew, r, q, (float)al_r, (float)al_i, first, rr, nr, ni);
-        double u3[3] = {rr, nr, ni};
-        block_reduce<3>(u3, red);
-        ++its;
-        rin = sqrt(u3[0]);
-        cdiv(u3[1], u3[2], rho_r, rho_i, br, bi);
-        rho_r = u3[1]; rho_i = u3[2];
-        first = false;
-        float2* t = pold; pold = pnew; pnew = t;
+      if (its >= a.maxit) { status = 1; break; }
+      ApplyPol<float> ap;
+      ap.r = r; ap.pold = pold; ap.pnew = pnew; ap.q = q; ap.v = a.v32;
+      ap.c0 = a.c32.c0; ap.eps = (float)eps; ap.om = (float)om; ap.br = (float)br;
+      ap.bi = (float)bi; ap.first = first;
+      ap.mu_re = ap.mu_im = 0.0;
+      march<float, FULL, HS, PITCH>(g, a.c32, ap, reinterpret_cast<float2*>(smem), 0, g.ntiles);
+      double m2[2] = {ap.mu_re, ap.mu_im};
+      block_reduce<2>(m2, red);
+      if (fabs(m2[0]) + fabs(m2[1]) < 1e-300) { status = 2; break; }
+      double al_r, al_i;
+      cdiv(rho_r, rho_i, m2[0], m2[1], al_r, al_i);
+      double rr = 0.0, nr = 0.0, ni = 0.0;
+      update_sweep<float, float>(N, d, pnew, r, q, (float)al_r, (float)al_i, dfresh, rr, nr, ni);
+      double u3[3] = {rr, nr, ni};
+      block_reduce<3>(u3, red);
+      ++its;
+      dfresh = false;
+      double rn = sqrt(u3[0]);
+      double rho_nr = u3[1], rho_ni = u3[2];
+      if ((rn < delta * rmax && its - last_upd >= kMinGap) || rn <= thr) {
+        // reliable update: x64 += d; r = b - A x64 in FP64 (stored rounded to FP32)
+        fold_sweep(N, x, d);
+        __syncthreads();
+        dfresh = true;
+        ++updates;
+        last_upd = its;
+        rp.rr = rp.bb = rp.rho_re = rp.rho_im = 0.0;
+        march_light<double, FULL, HS>(g, a.c64, rp, reinterpret_cast<double2*>(smem), 0, g.ntiles);
+        double w4[4] = {rp.rr, rp.bb, rp.rho_re, rp.rho_im};
+        block_reduce<4>(w4, red);
+        rn = sqrt(w4[0]);
+        rho_nr = w4[2];
+        rho_ni = w4[3];
+        rmax = rn;
+        if (rn < 0.5 * best_true) { best_true = rn; no_gain = 0; }
+        else if (++no_gain >= 4) { rnorm = rn; status = 1; break; }   // FP32 stagnation
       }
-      if (!first) fold_sweep(N, x, d);   // x64 += d
+      cdiv(rho_nr, rho_ni, rho_r, rho_i, br, bi);
+      rho_r = rho_nr; rho_i = rho_ni;
+      rnorm = rn;
+      first = false;
+      float2* t = pold; pold = pnew; pnew = t;
+    }
+    if (!dfresh) {                 // fold a pending correction (maxit / breakdown exits)
+      fold_sweep(N, x, d);
       __syncthreads();
-      ++cycles;
-      rp.rr = rp.bb = rp.rho_re = rp.rho_im = 0.0;
-      march<double, FULL>(g, a.c64, rp, reinterpret_cast<double2*>(smem), 0, g.ntiles);
-      double w4[4] = {rp.rr, rp.bb, rp.rho_re, rp.rho_im};
-      block_reduce<4>(w4, red);
-      rnorm = sqrt(w4[0]);
-      rho_r = w4[2]; rho_i = w4[3];
-      if (broke && rnorm > thr) { status = 2; break; }
     }
     if (status == 0 && !(rnorm <= thr)) status = 1;   // NaN residual is not convergence
   }
-  if (threadIdx.x == 0) record(a, s, its, cycles, status);
+  if (threadIdx.x == 0) record(a, s, its, updates, status);
 }
 
-template <bool REFINE, bool FULL>
+// M: 0 = tile covers the whole plane, 1 = y halo with one slot per thread,
+// 2 = y halo with two slots per thread.  PITCH: LDS row pitch (>= nz + 2R).
+template <bool REFINE, int M, int PITCH>
 __global__ void __launch_bounds__(kMaxBlock) k_cocg(CocgArgs a) {
+  constexpr bool FULL = M == 0;
+  constexpr int HS = M == 2 ? 2 : 1;
   extern __shared__ double smem_d[];
   char* smem = reinterpret_cast<char*>(smem_d);
   const Geom& g = a.g;
-  const int rows = FULL ? g.ny : g.ty + 2 * R;
-  double* red = reinterpret_cast<double*>(smem + (size_t)2 * rows * g.nz * sizeof(double2));
+  double* red = reinterpret_cast<double*>(smem + lds_plane_bytes(g, PITCH, REFINE));
   __shared__ int s_item;
   int item = 0;
   if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
@@ -521,8 +764,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_cocg(CocgArgs a) {
     const int b = s / a.n_occ;
     const int live = a.active == nullptr ? 1 : uni(a.active[b]);
     if (live) {
-      if (REFINE) solve_refine<FULL>(a, s, smem, red);
-      else solve_fp64<FULL>(a, s, smem, red);
+      if (REFINE) solve_refine<FULL, HS, PITCH>(a, s, smem, red);
+      else solve_fp64<FULL, HS, PITCH>(a, s, smem, red);
     } else if (threadIdx.x == 0) {
       a.out_iters[s] = 0;
       a.out_cycles[s] = 0;
@@ -535,52 +778,59 @@ __global__ void __launch_bounds__(kMaxBlock) k_cocg(CocgArgs a) {
   }
 }
 
-template <bool FULL>
-__global__ void __launch_bounds__(kMaxBlock) k_happly(Geom g, StencilCoef<double> c64,
-                                                       StencilCoef<float> c32, const double* v64,
-                                                       const float* v32, const double* sr,
-                                                       const double* si, const void* x, void* y,
-                                                       int fp32) {
+template <typename T, int M, int PITCH>
+__global__ void __launch_bounds__(kMaxBlock) k_happly(Geom g, StencilCoef<T> cf, const T* v,
+                                                       const double* sr, const double* si,
+                                                       const void* x, void* y) {
   extern __shared__ double smem_d[];
+  typedef typename V2<T>::t T2;
+  constexpr bool FULL = M == 0;
+  constexpr int HS = M == 2 ? 2 : 1;
   const int vec = blockIdx.y;
   const size_t base = (size_t)vec * g.N;
-  if (fp32) {
-    HPol<float> p;
-    p.x = reinterpret_cast<const float2*>(x) + base;
-    p.y = reinterpret_cast<float2*>(y) + base;
-    p.v = v32; p.c0 = c32.c0;
-    p.sr = (float)sr[vec]; p.si = (float)si[vec];
-    march<float, FULL>(g, c32, p, reinterpret_cast<float2*>(smem_d), blockIdx.x, blockIdx.x + 1);
-  } else {
-    HPol<double> p;
-    p.x = reinterpret_cast<const double2*>(x) + base;
-    p.y = reinterpret_cast<double2*>(y) + base;
-    p.v = v64; p.c0 = c64.c0; p.sr = sr[vec]; p.si = si[vec];
-    march<double, FULL>(g, c64, p, reinterpret_cast<double2*>(smem_d), blockIdx.x,
-                        blockIdx.x + 1);
-  }
+  HPol<T> p;
+  p.x = reinterpret_cast<const T2*>(x) + base;
+  p.y = reinterpret_cast<T2*>(y) + base;
+  p.v = v; p.c0 = cf.c0;
+  p.sr = (T)sr[vec]; p.si = (T)si[vec];
+  march<T, FULL, HS, PITCH>(g, cf, p, reinterpret_cast<T2*>(smem_d), blockIdx.x, blockIdx.x + 1);
 }
 
 }  // namespace
 
-size_t cocg_shmem_bytes(const Geom& g, int block, bool /*fp32_refine*/) {
-  const bool full = g.ty == g.ny;
-  const int rows = full ? g.ny : g.ty + 2 * R;
+namespace {
+int tile_mode(const Geom& g, int block) {
+  if (g.ty == g.ny) return 0;
+  return block >= 2 * R * g.nz ? 1 : 2;
+}
+int pitch_for(const Geom& g) { return g.nz + 2 * R <= 64 ? 64 : 128; }
+
+template <bool REFINE, int M>
+const void* cocg_fn_p(int pitch) {
+  return pitch == 64 ? reinterpret_cast<const void*>(&k_cocg<REFINE, M, 64>)
+                     : reinterpret_cast<const void*>(&k_cocg<REFINE, M, 128>);
+}
+template <bool REFINE>
+const void* cocg_fn(int m, int pitch) {
+  if (m == 0) return cocg_fn_p<REFINE, 0>(pitch);
+  if (m == 1) return cocg_fn_p<REFINE, 1>(pitch);
+  return cocg_fn_p<REFINE, 2>(pitch);
+}
+}  // namespace
+
+bool geom_supported(const Geom& g) { return g.nz + 2 * R <= 128; }
+
+size_t cocg_shmem_bytes(const Geom& g, int block, bool fp32_refine) {
   const int nw = (block + 63) / 64;
-  return (size_t)2 * rows * g.nz * sizeof(double2) + (size_t)(nw + 1) * 4 * sizeof(double);
+  return lds_plane_bytes(g, pitch_for(g), fp32_refine) + (size_t)(nw + 1) * 4 * sizeof(double);
 }
 
 int cocg_blocks_per_cu(const Geom& g, int block, bool fp32_refine) {
-  const bool full = g.ty == g.ny;
   const size_t shmem = cocg_shmem_bytes(g, block, fp32_refine);
+  const int m = tile_mode(g, block);
   int nb = 0;
-  hipError_t e;
-  if (fp32_refine)
-    e = full ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cocg<true, true>, block, shmem)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cocg<true, false>, block, shmem);
-  else
-    e = full ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cocg<false, true>, block, shmem)
-             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cocg<false, false>, block, shmem);
+  const void* fn = fp32_refine ? cocg_fn<true>(m, pitch_for(g)) : cocg_fn<false>(m, pitch_for(g));
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, shmem);
   if (e != hipSuccess || nb < 1) return 1;
   return nb;
 }
@@ -589,33 +839,64 @@ long long cocg_slot_bytes(const Geom& g, bool fp32_refine) {
   return fp32_refine ? 5LL * g.N * (long long)sizeof(float2) : 4LL * g.N * (long long)sizeof(double2);
 }
 
+namespace {
+template <bool REFINE, int M, int P>
+hipError_t launch_c(const CocgArgs& a, int grid, int block, size_t shmem, hipStream_t s) {
+  hipLaunchKernelGGL((k_cocg<REFINE, M, P>), dim3(grid), dim3(block), shmem, s, a);
+  return hipGetLastError();
+}
+template <bool REFINE, int M>
+hipError_t launch_cm(const CocgArgs& a, int pitch, int grid, int block, size_t shmem, hipStream_t s) {
+  return pitch == 64 ? launch_c<REFINE, M, 64>(a, grid, block, shmem, s)
+                     : launch_c<REFINE, M, 128>(a, grid, block, shmem, s);
+}
+template <typename T, int M, int P>
+hipError_t launch_h(const Geom& g, const StencilCoef<T>& cf, const T* v, const double* sr,
+                    const double* si, const void* x, void* y, dim3 grid, int block, size_t shmem,
+                    hipStream_t s) {
+  hipLaunchKernelGGL((k_happly<T, M, P>), grid, dim3(block), shmem, s, g, cf, v, sr, si, x, y);
+  return hipGetLastError();
+}
+template <typename T, int M>
+hipError_t launch_hm(const Geom& g, const StencilCoef<T>& cf, const T* v, const double* sr,
+                     const double* si, const void* x, void* y, dim3 grid, int block,
+                     size_t shmem, hipStream_t s) {
+  return pitch_for(g) == 64 ? launch_h<T, M, 64>(g, cf, v, sr, si, x, y, grid, block, shmem, s)
+                            : launch_h<T, M, 128>(g, cf, v, sr, si, x, y, grid, block, shmem, s);
+}
+template <typename T>
+hipError_t launch_ht(const Geom& g, const StencilCoef<T>& cf, const T* v, const double* sr,
+                     const double* si, const void* x, void* y, dim3 grid, int block,
+                     size_t shmem, hipStream_t s) {
+  const int m = tile_mode(g, block);
+  if (m == 0) return launch_hm<T, 0>(g, cf, v, sr, si, x, y, grid, block, shmem, s);
+  if (m == 1) return launch_hm<T, 1>(g, cf, v, sr, si, x, y, grid, block, shmem, s);
+  return launch_hm<T, 2>(g, cf, v, sr, si, x, y, grid, block, shmem, s);
+}
+}  // namespace
+
 hipError_t launch_cocg(const CocgArgs& a, bool fp32_refine, int grid, int block, size_t shmem,
                        hipStream_t s) {
-  const bool full = a.g.ty == a.g.ny;
+  const int m = tile_mode(a.g, block);
+  const int pitch = pitch_for(a.g);
   if (fp32_refine) {
-    if (full) hipLaunchKernelGGL((k_cocg<true, true>), dim3(grid), dim3(block), shmem, s, a);
-    else hipLaunchKernelGGL((k_cocg<true, false>), dim3(grid), dim3(block), shmem, s, a);
-  } else {
-    if (full) hipLaunchKernelGGL((k_cocg<false, true>), dim3(grid), dim3(block), shmem, s, a);
-    else hipLaunchKernelGGL((k_cocg<false, false>), dim3(grid), dim3(block), shmem, s, a);
+    if (m == 0) return launch_cm<true, 0>(a, pitch, grid, block, shmem, s);
+    if (m == 1) return launch_cm<true, 1>(a, pitch, grid, block, shmem, s);
+    return launch_cm<true, 2>(a, pitch, grid, block, shmem, s);
   }
-  return hipGetLastError();
+  if (m == 0) return launch_cm<false, 0>(a, pitch, grid, block, shmem, s);
+  if (m == 1) return launch_cm<false, 1>(a, pitch, grid, block, shmem, s);
+  return launch_cm<false, 2>(a, pitch, grid, block, shmem, s);
 }
 
 hipError_t launch_happly(const Geom& g, const StencilCoef<double>& c64, const StencilCoef<float>& c32,
                          const double* v64, const float* v32, int nvec, const double* shift_re,
                          const double* shift_im, const void* x, void* y, bool fp32,
                          int block, hipStream_t s) {
-  const bool full = g.ty == g.ny;
-  const size_t shmem = cocg_shmem_bytes(g, block, false);
+  const size_t shmem = cocg_shmem_bytes(g, block, fp32);
   dim3 grid(g.ntiles, nvec);
-  if (full)
-    hipLaunchKernelGGL((k_happly<true>), grid, dim3(block), shmem, s, g, c64, c32, v64, v32,
-                       shift_re, shift_im, x, y, fp32 ? 1 : 0);
-  else
-    hipLaunchKernelGGL((k_happly<false>), grid, dim3(block), shmem, s, g, c64, c32, v64, v32,
-                       shift_re, shift_im, x, y, fp32 ? 1 : 0);
-  return hipGetLastError();
+  if (fp32) return launch_ht<float>(g, c32, v32, shift_re, shift_im, x, y, grid, block, shmem, s);
+  return launch_ht<double>(g, c64, v64, shift_re, shift_im, x, y, grid, block, shmem, s);
 }
 
 }  // namespace rpa

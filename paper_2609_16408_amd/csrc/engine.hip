@@ -294,7 +294,7 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
   a.tol = h->tol;
   a.maxit = h->maxit;
   a.inner_tol = h->inner_tol;
-  a.max_cycles = 50;
+  a.max_cycles = 0;
   const size_t shmem = cocg_shmem_bytes(h->geom, h->block, refine);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   {
@@ -487,6 +487,11 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   ARG_CHECK(ty > 0 && ny % ty == 0 && ((ty * nz + 63) / 64) * 64 <= kMaxBlock,
             "no valid tile_y (ty | ny, ty*nz <= 768)");
   ARG_CHECK(ty == ny || ty >= kRadius, "tile_y must be >= 6 unless it covers the plane");
+  {
+    Geom gq;
+    gq.nx = p->n[0]; gq.ny = ny; gq.nz = nz; gq.ty = ty; gq.ntiles = ny / ty; gq.N = N;
+    ARG_CHECK(geom_supported(gq), "n[2] must be <= 116");
+  }
 
   rpa_ctx* h = new rpa_ctx();
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -503,7 +508,9 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   h->maxit = p->stern_maxit;
   h->batch = p->batch;
   h->budget = p->hbm_budget;
-  h->inner_tol = p->inner_tol > 0 ? p->inner_tol : 1e-5;
+  // reliable-update factor of the FP32 COCG (residual replaced by the FP64
+  // residual each time the recursive one dropped by this factor)
+  h->inner_tol = p->inner_tol > 0 ? p->inner_tol : 0.1;
   h->slots_per_cu = p->slots_per_cu;
   h->geom.nx = p->n[0];
   h->geom.ny = ny;
@@ -530,16 +537,16 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   for (int d = 0; d < 3; ++d) inv2 += 1.0 / (h->h[d] * h->h[d]);
   h->c64.c0 = -0.5 * w[0] * inv2;
   h->c32.c0 = (float)h->c64.c0;
-  h->c64.cx[0] = h->c64.cy[0] = h->c64.cz[0] = 0.0;
-  h->c32.cx[0] = h->c32.cy[0] = h->c32.cz[0] = 0.f;
-  for (int k = 1; k <= kRadius; ++k) {
-    h->c64.cx[k] = -0.5 * w[k] / (h->h[0] * h->h[0]);
-    h->c64.cy[k] = -0.5 * w[k] / (h->h[1] * h->h[1]);
-    h->c64.cz[k] = -0.5 * w[k] / (h->h[2] * h->h[2]);
-    h->c32.cx[k] = (float)h->c64.cx[k];
-    h->c32.cy[k] = (float)h->c64.cy[k];
-    h->c32.cz[k] = (float)h->c64.cz[k];
+  for (int k = 0; k <= kRadius; ++k) {
+    h->c64.w[k] = w[k];
+    h->c32.w[k] = (float)w[k];
   }
+  h->c64.sx = -0.5 / (h->h[0] * h->h[0]);
+  h->c64.sy = -0.5 / (h->h[1] * h->h[1]);
+  h->c64.sz = -0.5 / (h->h[2] * h->h[2]);
+  h->c32.sx = (float)h->c64.sx;
+  h->c32.sy = (float)h->c64.sy;
+  h->c32.sz = (float)h->c64.sz;
 
   // resident copies
   DevBuf b;

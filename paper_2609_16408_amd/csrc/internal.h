@@ -11,13 +11,14 @@ constexpr int kRadius = 6;               // 12th-order central differences
 constexpr int kMaxLanczos = 64;          // largest supported n_lanczos
 constexpr int kMaxBlock = 768;           // largest stencil/COCG workgroup
 
-// (H - eps_n - i omega) p = (c0 + V - eps_n) p - i omega p + sum_d sum_k c_d[k] (p_{+k} + p_{-k})
+// (H - eps_n - i omega) p = (c0 + V - eps_n) p - i omega p
+//                          + sum_d s_d sum_k w[k] (p_{+k e_d} + p_{-k e_d}),
+// w[k] the unit-spacing FD weights, s_d = -1/(2 h_d^2), c0 = -1/2 w_0 sum_d 1/h_d^2.
 template <typename T>
 struct StencilCoef {
   T c0;
-  T cx[kRadius + 1];
-  T cy[kRadius + 1];
-  T cz[kRadius + 1];
+  T w[kRadius + 1];
+  T sx, sy, sz;
 };
 
 struct Geom {
@@ -61,6 +62,7 @@ hipError_t launch_cocg(const CocgArgs& a, bool fp32_refine, int grid, int block,
                        hipStream_t s);
 size_t cocg_shmem_bytes(const Geom& g, int block, bool fp32_refine);
 int cocg_blocks_per_cu(const Geom& g, int block, bool fp32_refine);
+bool geom_supported(const Geom& g);   // nz + 12 <= 128 (padded LDS rows)
 long long cocg_slot_bytes(const Geom& g, bool fp32_refine);
 
 hipError_t launch_happly(const Geom& g, const StencilCoef<double>& c64, const StencilCoef<float>& c32,

@@ -49,7 +49,9 @@ def _cplx(shape, seed):
 # --- stencil ------------------------------------------------------------------
 
 @pytest.mark.parametrize("grid,tile_y", [((12, 12, 12), 0), ((12, 12, 12), 6),
-                                          ((9, 40, 24), 0), ((8, 30, 10), 10)])
+                                          ((9, 40, 24), 0), ((8, 30, 10), 10), ((7, 14, 8), 7),
+                                          ((8, 10, 72), 0), ((9, 24, 72), 0), ((40, 12, 12), 0),
+                                          ((50, 30, 10), 10), ((36, 40, 24), 0)])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
 def test_hamiltonian_apply_matches_oracle(P, grid, tile_y, precision):
     L = (10.26 * grid[0] / 12, 10.26 * grid[1] / 12, 10.26 * grid[2] / 12)
@@ -100,6 +102,32 @@ def test_chi0_apply_matches_oracle(P, tiny, tiny_ops, omega, symmetrized):
         r = O.chi0_apply(ham, tiny.psi, tiny.eps, u, omega, tol=1e-10)
         ref = coul.half(r) if symmetrized else r
         assert np.abs(y[i] - ref).max() <= 1e-8 * np.abs(ref).max(), i
+    h.close()
+
+
+@pytest.fixture(scope="module")
+def long_cell():
+    """3x2x1 cell on a 36 x 24 x 12 grid: nx exceeds every register-pipeline
+    length, and tile_y selects whole-plane, one-slot and two-slot halo tiles."""
+    c = sc.make_cell("long", cells=(3, 2, 1), n=(36, 24, 12), n_occ=16, seed=9)
+    sc.ks_orbitals(c)
+    return c
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+@pytest.mark.parametrize("tile_y", [0, 12, 6])
+def test_chi0_apply_long_cell_all_tile_modes(P, long_cell, precision, tile_y):
+    c = long_cell
+    ham = O.Hamiltonian(c.n, c.L, c.v_loc)
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    h = _handle(P, c, precision=precision, stern_tol=tol, tile_y=tile_y)
+    x = np.random.default_rng(21).standard_normal((2, c.N_d))
+    y, st = h.chi0_apply(0.31, torch.from_numpy(x))
+    y = y.cpu().numpy()
+    assert st["n_noconv"] == 0
+    for i in range(2):
+        ref = O.chi0_apply(ham, c.psi, c.eps, x[i], 0.31, tol=1e-11)
+        assert np.abs(y[i] - ref).max() <= 20 * tol * np.abs(ref).max(), (i, np.abs(y[i] - ref).max())
     h.close()
 
 
