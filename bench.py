@@ -23,6 +23,9 @@ if ROOT not in sys.path:
 
 METRIC = "RPA energy-density points/s, Si64 FP32+refine vs FP64; stencil GB/s; p99 latency"
 HBM_PEAK_GBPS = 8000.0
+COCG_SRC = os.path.join(ROOT, "paper_2609_16408_amd", "csrc", "cocg.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_cocg_si64_hbm_traffic.md")
+CALIB_BYTES = 1 << 30
 
 # workload name -> synthetic cell preset and method settings
 WORKLOADS = {
@@ -53,6 +56,56 @@ def cocg_algorithmic_bytes(st: dict, N: int, precision: str) -> float:
     else:
         per_pt = 160.0 * st["cocg_iters_total"] + 48.0 * st["n_systems"]
     return per_pt * N
+
+
+def source_sha():
+    import hashlib
+    return hashlib.sha256(open(COCG_SRC, "rb").read()).hexdigest()[:16]
+
+
+def pmc_traffic(workload):
+    """HBM bytes per k_cocg launch from the committed rocprofv3 --pmc summary,
+    or None when it is missing, for another workload, or for another version
+    of the kernel source."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    vals = {}
+    for line in open(PMC_SUMMARY):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("workload") != workload or vals.get("cocg_source_sha") != source_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def calibrate_copy():
+    """Plain device-to-device copy of CALIB_BYTES (the rocprofv3 --pmc scale reference)."""
+    import torch
+    src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": CALIB_BYTES, "copies": 3}), flush=True)
+
+
+def load_or_make_cell(sc, preset, cache):
+    """Synthetic cell; with `cache`, orbitals are reused from (or saved to) an .npz."""
+    import numpy as np
+    if cache and os.path.exists(cache):
+        cell = sc.preset(preset, orbitals=False)
+        z = np.load(cache)
+        cell.psi, cell.eps = z["psi"], z["eps"]
+        cell.gap, cell.eig_residual = float(z["gap"]), float(z["res"])
+        return cell
+    cell = sc.preset(preset, device="cuda")
+    if cache:
+        np.savez(cache, psi=cell.psi, eps=cell.eps, gap=cell.gap, res=cell.eig_residual)
+    return cell
 
 
 def stencil_gbps(P, h, cell, torch, nvec=512, reps=5):
@@ -105,7 +158,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slots-per-cu", type=int, default=0)
     ap.add_argument("--tile-y", type=int, default=0)
+    ap.add_argument("--orbital-cache", default="", help="npz file to reuse/save the orbitals")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run the plain copy used to scale HBM counters")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the per-point work "
               "is independent, so N GPUs shard the (point, frequency) list with no communication "
@@ -120,7 +179,7 @@ def main():
     cfg = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    cell = sc.preset(cfg["preset"], device="cuda")
+    cell = load_or_make_cell(sc, cfg["preset"], args.orbital_cache)
     log(f"[bench] cell {cfg['preset']} n={cell.n} N_s={cell.n_occ} gap={cell.gap:.2e} "
         f"eig residual={cell.eig_residual:.1e} setup {time.perf_counter() - t0:.1f}s")
     omega, weight = P.frequency_rule(8)
@@ -174,6 +233,7 @@ def main():
                                                  "n_noconv", "n_breakdown")}
     alg_bytes = cocg_algorithmic_bytes(tot, cell.N_d, args.precision)
     achieved = alg_bytes / (cocg_ms * 1e-3) / 1e9
+    traffic = pmc_traffic(args.workload) if args.precision == "fp32_refine" else None
     timing = h.last_cocg_timing()
 
     extra = {}
@@ -220,8 +280,9 @@ def main():
                    "points_per_step": pps * 8, "coarse_stride": stride,
                    "interp": cfg["interp"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "k_cocg (batched Sternheimer COCG)",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": alg_bytes / max(1, cocg_launches),
+                     "kernel": "k_cocg (batched Sternheimer COCG)", "cocg_source_sha": source_sha(),
                      "launches": cocg_launches, "avg_launch_ms": cocg_ms / max(1, cocg_launches),
                      "grid": timing["grid"], "block": timing["block"], "tile_y": timing["tile_y"]},
         "cpu_baseline": cpu,
