@@ -84,6 +84,10 @@ typedef struct {
   double inner_tol;           /* RPA_FP32_REFINE: the FP32 recursive residual is replaced
                                  by the FP64 residual each time it drops by this
                                  factor (reliable update); in (0, 1), 0 = 0.1 */
+  int32_t use_graph;          /* != 0: lanczos_energy_density captures the per-batch
+                                 launch sequence (all Lanczos steps) into a hipGraph
+                                 and replays it for later batches of the same size;
+                                 per-launch COCG timing is then not recorded */
 } rpa_setup_params;
 
 typedef struct {
@@ -179,6 +183,46 @@ rpa_status rpa_coulomb_apply(rpa_handle h, int32_t power, int32_t nvec, const do
  * output pointer may be NULL.  For measurement only. */
 rpa_status rpa_last_cocg_timing(rpa_handle h, double* ms, int32_t* launches, int32_t* grid,
                                 int32_t* block, int32_t* tile_y);
+
+/* Release every workspace of the handle (resident problem data stays). */
+rpa_status rpa_release_workspace(rpa_handle h);
+
+/* Serving -------------------------------------------------------------------
+ * Energy-density jobs (cell, one frequency omega, a block of points, N_l) are
+ * queued and run by worker threads, each with its own HIP stream, so jobs
+ * that arrive while others run overlap on the device.  A job is admitted
+ * (oldest first) when a worker is idle and its workspace estimate fits the
+ * HBM budget next to the resident cell data; a job that can never fit is
+ * refused at submission with RPA_E_OOM.  Start vectors are batched inside a
+ * job only, so a job's result is the same alone and in any mix.  Paper:
+ * Algorithm 1 point loop; the jobs play the role of the per-rank point
+ * blocks of the Implementation section. */
+typedef struct rpa_server_s* rpa_server;
+typedef struct {
+  int32_t n_workers;          /* concurrent jobs (1..16) */
+  uint64_t hbm_budget;        /* bytes; 0 = no cap */
+  int32_t fake_executor_us;   /* > 0: jobs sleep this long instead of computing
+                                 (host-only tests of admission and timing) */
+} rpa_server_params;
+typedef struct {
+  int32_t status;             /* rpa_status of the job, -1 while pending */
+  double t_submit, t_start, t_finish;   /* host steady clock, seconds */
+  int64_t footprint;          /* admitted workspace estimate, bytes */
+  rpa_stats stats;
+} rpa_job_info;
+
+rpa_status rpa_server_create(const rpa_server_params* p, rpa_server* out);
+/* Register a cell (device data is copied; eps host) and return its id. */
+rpa_status rpa_server_add_cell(rpa_server s, const rpa_setup_params* p, int32_t* cell_id);
+/* Queue a job; pts [host] are copied; d_out [dev] FP64 [n_pts] receives d_j(omega). */
+rpa_status rpa_server_submit(rpa_server s, int32_t cell_id, double omega, int32_t n_pts,
+                             const int64_t* pts, int32_t n_lanczos, double* d_out,
+                             int64_t* job_id);
+/* Block until the job has finished; info (host) receives its record. */
+rpa_status rpa_server_wait(rpa_server s, int64_t job_id, rpa_job_info* info);
+rpa_status rpa_server_status(rpa_server s, int32_t* waiting, int32_t* running, uint64_t* in_use);
+/* Finish every queued job, stop the workers and free the cells. */
+rpa_status rpa_server_destroy(rpa_server s);
 
 #ifdef __cplusplus
 }

@@ -44,6 +44,7 @@ class SetupParams(ctypes.Structure):
         ("stern_maxit", ctypes.c_int32), ("batch", ctypes.c_int32),
         ("hbm_budget", ctypes.c_uint64), ("tile_y", ctypes.c_int32),
         ("slots_per_cu", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+        ("use_graph", ctypes.c_int32),
     ]
 
 
@@ -57,6 +58,23 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerParams(ctypes.Structure):
+    _fields_ = [("n_workers", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64),
+                ("fake_executor_us", ctypes.c_int32)]
+
+
+class JobInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_finish", ctypes.c_double),
+                ("footprint", ctypes.c_int64), ("stats", Stats)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "stats"}
+        d["stats"] = self.stats.as_dict()
+        d["latency"] = self.t_finish - self.t_submit
+        return d
 
 
 _VP, _I32, _D, _I64P = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
@@ -73,6 +91,13 @@ _SIGS = {
     "rpa_hamiltonian_apply": [_VP, _I32, _VP, _VP, _VP, _VP, _I32, _VP],
     "rpa_coulomb_apply": [_VP, _I32, _I32, _VP, _VP, _VP],
     "rpa_last_cocg_timing": [_VP, _VP, _VP, _VP, _VP, _VP],
+    "rpa_release_workspace": [_VP],
+    "rpa_server_create": [_VP, _VP],
+    "rpa_server_add_cell": [_VP, ctypes.POINTER(SetupParams), _VP],
+    "rpa_server_submit": [_VP, _I32, _D, _I32, _VP, _I32, _VP, _VP],
+    "rpa_server_wait": [_VP, ctypes.c_int64, _VP],
+    "rpa_server_status": [_VP, _VP, _VP, _VP],
+    "rpa_server_destroy": [_VP],
 }
 
 
@@ -134,7 +159,7 @@ class Handle:
 
     def __init__(self, n, L, v_loc, psi, eps, precision="fp64", stern_tol=1e-10,
                  stern_maxit=20000, batch=0, tile_y=0, slots_per_cu=0, inner_tol=0.0,
-                 hbm_budget=0, stream=None):
+                 hbm_budget=0, use_graph=False, stream=None):
         import torch
         self._torch = torch
         dev = torch.device("cuda")
@@ -165,10 +190,15 @@ class Handle:
         prm.tile_y = int(tile_y)
         prm.slots_per_cu = int(slots_per_cu)
         prm.inner_tol = float(inner_tol)
+        prm.use_graph = 1 if use_graph else 0
         h = ctypes.c_void_p()
         _check(lib().rpa_setup(ctypes.byref(prm), _stream(stream), ctypes.byref(h)), "rpa_setup")
         self._h = h
         self.precision = precision
+
+    def release_workspace(self):
+        """Free the workspaces (resident cell data stays); captured graphs are dropped."""
+        _check(lib().rpa_release_workspace(self._h), "rpa_release_workspace")
 
     def close(self):
         if getattr(self, "_h", None):
@@ -267,6 +297,96 @@ class Handle:
                                           ctypes.byref(ty)), "rpa_last_cocg_timing")
         return {"ms": ms.value, "launches": launches.value, "grid": grid.value,
                 "block": block.value, "tile_y": ty.value}
+
+
+def _setup_params(n, L, v_ptr, psi_ptr, eps, precision, stern_tol, stern_maxit, batch=0,
+                  tile_y=0, slots_per_cu=0, inner_tol=0.0, hbm_budget=0):
+    prm = SetupParams()
+    prm.n[:] = tuple(int(x) for x in n)
+    prm.L[:] = tuple(float(x) for x in L)
+    prm.fd_radius = 6
+    prm.n_occ = int(eps.size)
+    prm.v_loc = v_ptr
+    prm.psi = psi_ptr
+    prm.eps = eps.ctypes.data
+    prm.n_proj = 0
+    prm.precision = PRECISION[precision]
+    prm.stern_tol = float(stern_tol)
+    prm.stern_maxit = int(stern_maxit)
+    prm.batch = int(batch)
+    prm.hbm_budget = int(hbm_budget)
+    prm.tile_y = int(tile_y)
+    prm.slots_per_cu = int(slots_per_cu)
+    prm.inner_tol = float(inner_tol)
+    return prm
+
+
+class Server:
+    """Energy-density serving loop (rpa_server_* of the C ABI)."""
+
+    def __init__(self, n_workers=3, hbm_budget=0, fake_executor_us=0):
+        p = ServerParams(int(n_workers), int(hbm_budget), int(fake_executor_us))
+        h = ctypes.c_void_p()
+        _check(lib().rpa_server_create(ctypes.byref(p), ctypes.byref(h)), "rpa_server_create")
+        self._h = h
+        self.fake = fake_executor_us > 0
+        self._keep = {}
+        self._out = {}
+
+    def add_cell(self, n, L, v_loc, psi, eps, precision="fp32_refine", stern_tol=1e-6,
+                 stern_maxit=20000, batch=0):
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        if self.fake:
+            prm = _setup_params(n, L, None, None, eps, precision, stern_tol, stern_maxit, batch)
+        else:
+            import torch
+            v = torch.as_tensor(np.ascontiguousarray(v_loc, dtype=np.float64)).cuda()
+            p = torch.as_tensor(np.ascontiguousarray(psi, dtype=np.float64)).cuda()
+            prm = _setup_params(n, L, v.data_ptr(), p.data_ptr(), eps, precision, stern_tol,
+                                stern_maxit, batch)
+        cid = ctypes.c_int32()
+        _check(lib().rpa_server_add_cell(self._h, ctypes.byref(prm), ctypes.byref(cid)),
+               "rpa_server_add_cell")
+        self._keep[cid.value] = eps
+        return cid.value
+
+    def submit(self, cell_id, omega, points, n_lanczos):
+        pts = np.ascontiguousarray(points, dtype=np.int64)
+        out = None
+        if not self.fake:
+            import torch
+            out = torch.empty(pts.size, dtype=torch.float64, device="cuda")
+        jid = ctypes.c_int64()
+        _check(lib().rpa_server_submit(self._h, int(cell_id), float(omega), pts.size,
+                                       pts.ctypes.data, int(n_lanczos),
+                                       _ptr(out) if out is not None else None, ctypes.byref(jid)),
+               "rpa_server_submit")
+        self._out[jid.value] = out
+        return jid.value
+
+    def wait(self, job_id):
+        info = JobInfo()
+        _check(lib().rpa_server_wait(self._h, ctypes.c_int64(job_id), ctypes.byref(info)),
+               "rpa_server_wait")
+        return self._out.pop(job_id, None), info.as_dict()
+
+    def status(self):
+        w, r = ctypes.c_int32(), ctypes.c_int32()
+        u = ctypes.c_uint64()
+        _check(lib().rpa_server_status(self._h, ctypes.byref(w), ctypes.byref(r), ctypes.byref(u)),
+               "rpa_server_status")
+        return {"waiting": w.value, "running": r.value, "in_use": u.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rpa_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def handle_for_cell(cell, **kw) -> Handle:

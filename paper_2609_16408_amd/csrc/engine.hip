@@ -63,6 +63,15 @@ struct rpa_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   float last_ms = 0.f;
   int last_grid = 0;
+  int use_graph = 0;
+  bool capturing = false;
+  unsigned alloc_epoch = 0;          // bumped whenever a workspace is (re)allocated
+  int warm_B = 0, warm_m = 0;        // largest batch run eagerly with the current buffers
+  hipStream_t cap_stream = nullptr;  // non-default stream used for capture
+  struct GraphEntry { hipGraph_t g; hipGraphExec_t e; unsigned epoch; };
+  std::vector<std::pair<std::pair<int, int>, GraphEntry>> graphs;
+  DevBuf dres;
+  std::vector<int> order_h;
   std::vector<hipEvent_t> evs;   // COCG launch timing events of the current call
   int n_ev_used = 0;
   double cocg_ms_total = 0.0;
@@ -92,6 +101,8 @@ rpa_status set_err(rpa_status s, const std::string& msg) {
 
 rpa_status ensure(rpa_ctx* h, DevBuf& b, size_t bytes) {
   if (b.bytes >= bytes && b.p) return RPA_OK;
+  if (h->capturing) return set_err(RPA_E_STATE, "allocation requested during graph capture");
+  ++h->alloc_epoch;
   if (b.p) {
     hipError_t e = hipFree(b.p);
     if (e != hipSuccess) { h->broken = true; return set_err(RPA_E_HIP, "hipFree failed"); }
@@ -208,6 +219,7 @@ rpa_status usable(rpa_ctx* h) {
 }
 
 rpa_status cocg_events(rpa_ctx* h, hipEvent_t* e0, hipEvent_t* e1);
+void drop_graphs(rpa_ctx* h);
 
 // u[B][N] -> out[B][N] = nu^(power/2) u  (Kronecker form; tmp buffers internal)
 rpa_status coulomb(rpa_ctx* h, int power, int B, const double* in, double* out, hipStream_t s) {
@@ -231,8 +243,28 @@ rpa_status coulomb(rpa_ctx* h, int power, int B, const double* in, double* out, 
 
 // Sternheimer batch: given u (B start vectors at per-vector omega, already in
 // h->u64), solve all B*nocc systems and accumulate racc[B][N].
+// Processing order of the B*N_s systems: smallest omega first, then the
+// highest orbital (the longest solves start first).  Host-to-device copy.
+rpa_status upload_order_for(rpa_ctx* h, int B, const std::vector<double>& omega_host, hipStream_t s) {
+  const int nocc = h->nocc;
+  const int n_items = B * nocc;
+  ENSURE(h, h->order, (size_t)n_items * sizeof(int));
+  h->order_h.resize(n_items);
+  std::vector<int>& order = h->order_h;
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const double wa = omega_host[a / nocc], wb = omega_host[b / nocc];
+    if (wa != wb) return wa < wb;
+    return (a % nocc) > (b % nocc);
+  });
+  HIPCHK(h, hipMemcpyAsync(h->order.p, order.data(), n_items * sizeof(int), hipMemcpyHostToDevice, s));
+  return RPA_OK;
+}
+
 rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega_host,
-                             const int* active_dev, hipStream_t s) {
+                             const int* active_dev, hipStream_t s, bool upload_order = true,
+                             bool timing = true) {
+  rpa_status r_ = RPA_OK;
   const long long N = h->N;
   const int nocc = h->nocc;
   const bool refine = h->precision == RPA_FP32_REFINE;
@@ -247,20 +279,15 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
                                P<double>(h->omega_b), P<double2>(h->G), s));
   HIPCHK(h, launch_expand(h->psi64, P<double2>(h->G), B, nocc, N, P<double2>(h->x64), s));
 
-  // processing order: smallest omega first, then highest orbital (longest solves first)
-  std::vector<int> order(n_items);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    const double wa = omega_host[a / nocc], wb = omega_host[b / nocc];
-    if (wa != wb) return wa < wb;
-    return (a % nocc) > (b % nocc);
-  });
   ENSURE(h, h->order, (size_t)n_items * sizeof(int));
   ENSURE(h, h->iters, (size_t)n_items * sizeof(int));
   ENSURE(h, h->cycles, (size_t)n_items * sizeof(int));
   ENSURE(h, h->status, (size_t)n_items * sizeof(int));
   ENSURE(h, h->counter, sizeof(int) * 64);
-  HIPCHK(h, hipMemcpyAsync(h->order.p, order.data(), n_items * sizeof(int), hipMemcpyHostToDevice, s));
+  if (upload_order) {
+    r_ = upload_order_for(h, B, omega_host, s);
+    if (r_ != RPA_OK) return r_;
+  }
   HIPCHK(h, launch_fill_i(P<int>(h->counter), 0, 1, s));
 
   const int bpc = h->slots_per_cu > 0 ? h->slots_per_cu : cocg_blocks_per_cu(h->geom, h->block, refine);
@@ -296,14 +323,16 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
   a.inner_tol = h->inner_tol;
   a.max_cycles = 0;
   const size_t shmem = cocg_shmem_bytes(h->geom, h->block, refine);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  {
+  if (timing) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     rpa_status es = cocg_events(h, &e0, &e1);
     if (es != RPA_OK) return es;
+    HIPCHK(h, hipEventRecord(e0, s));
+    HIPCHK(h, launch_cocg(a, refine, grid, h->block, shmem, s));
+    HIPCHK(h, hipEventRecord(e1, s));
+  } else {
+    HIPCHK(h, launch_cocg(a, refine, grid, h->block, shmem, s));
   }
-  HIPCHK(h, hipEventRecord(e0, s));
-  HIPCHK(h, launch_cocg(a, refine, grid, h->block, shmem, s));
-  HIPCHK(h, hipEventRecord(e1, s));
   h->last_grid = grid;
 
   ENSURE(h, h->racc, (size_t)B * N * sizeof(double));
@@ -512,6 +541,7 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   // residual each time the recursive one dropped by this factor)
   h->inner_tol = p->inner_tol > 0 ? p->inner_tol : 0.1;
   h->slots_per_cu = p->slots_per_cu;
+  h->use_graph = p->use_graph;
   h->geom.nx = p->n[0];
   h->geom.ny = ny;
   h->geom.nz = nz;
@@ -607,10 +637,34 @@ rpa_status rpa_destroy(rpa_handle h) {
                     &h->counter, &h->stats, &h->omega_b, &h->pos_b, &h->idx_b, &h->gpart, &h->G,
                     &h->dhat, &h->partials, &h->interp_m, &h->shifts, &h->fail};
   for (DevBuf* b : bufs) fr(b->p);
+  drop_graphs(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  fr(h->dres.p);
   for (hipEvent_t e : h->evs) (void)hipEventDestroy(e);
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
   delete h;
+  return RPA_OK;
+}
+
+rpa_status rpa_release_workspace(rpa_handle h) {
+  if (!h) return set_err(RPA_E_ARG, "null handle");
+  if (hipDeviceSynchronize() != hipSuccess) (void)hipGetLastError();
+  drop_graphs(h);
+  h->warm_B = 0;
+  h->warm_m = 0;
+  ++h->alloc_epoch;
+  DevBuf* bufs[] = {&h->x64, &h->slots, &h->u64, &h->racc, &h->vtmp, &h->tmpA, &h->Q, &h->alpha,
+                    &h->beta, &h->mlen, &h->active, &h->order, &h->iters, &h->cycles, &h->status,
+                    &h->counter, &h->gpart, &h->G, &h->dhat, &h->partials, &h->shifts, &h->dres};
+  for (DevBuf* b : bufs) {
+    if (b->p) {
+      (void)hipFree(b->p);
+      h->allocated -= b->bytes;
+      b->p = nullptr;
+      b->bytes = 0;
+    }
+  }
   return RPA_OK;
 }
 
@@ -690,6 +744,94 @@ rpa_status chi0_apply(rpa_handle h, double omega, int32_t nvec, const double* x,
   return end_stats(h, s, st, t0, (long long)nvec * h->nocc, 0);
 }
 
+}  // extern "C"
+namespace {
+
+// The whole per-batch sequence: q_1 = e_j, then per Lanczos step nu^1/2,
+// Galerkin guess, persistent COCG, accumulation, nu^1/2, Lanczos update; then
+// the tridiagonal quadrature into dres.  Kernels only (no copies), so it can
+// be captured into a graph once the workspaces exist.
+rpa_status enqueue_batch(rpa_ctx* h, int nb, int m, hipStream_t s, bool timing) {
+  const long long N = h->N;
+  rpa_status r = RPA_OK;
+  HIPCHK(h, launch_fill_d(P<double>(h->Q), 0.0, (long long)m * nb * N, s));
+  HIPCHK(h, launch_set_onehot(P<double>(h->Q), N, P<long long>(h->idx_b), nb, s));
+  HIPCHK(h, launch_fill_i(P<int>(h->active), 1, nb, s));
+  HIPCHK(h, launch_fill_i(P<int>(h->mlen), 0, nb, s));
+  HIPCHK(h, launch_fill_d(P<double>(h->alpha), 0.0, (long long)nb * m, s));
+  HIPCHK(h, launch_fill_d(P<double>(h->beta), 0.0, (long long)nb * m, s));
+  static const std::vector<double> none;
+  for (int k = 0; k < m; ++k) {
+    double* qk = P<double>(h->Q) + (size_t)k * nb * N;
+    r = coulomb(h, 1, nb, qk, P<double>(h->u64), s);
+    if (r != RPA_OK) return r;
+    r = sternheimer_batch(h, nb, none, P<int>(h->active), s, false, timing);
+    if (r != RPA_OK) return r;
+    // v = nu^1/2 racc  (written into u64, which is free again)
+    r = coulomb(h, 1, nb, P<double>(h->racc), P<double>(h->u64), s);
+    if (r != RPA_OK) return r;
+    HIPCHK(h, launch_lanczos_step(k, m, nb, N, P<double>(h->Q), P<double>(h->u64),
+                                  P<double>(h->alpha), P<double>(h->beta), P<int>(h->mlen),
+                                  P<int>(h->active), 1e-13, s));
+  }
+  HIPCHK(h, launch_tridiag_quad(nb, m, P<double>(h->alpha), P<double>(h->beta), P<int>(h->mlen),
+                                nullptr, P<double>(h->dres), P<int>(h->fail), s));
+  return RPA_OK;
+}
+
+void drop_graphs(rpa_ctx* h) {
+  for (auto& kv : h->graphs) {
+    (void)hipGraphExecDestroy(kv.second.e);
+    (void)hipGraphDestroy(kv.second.g);
+  }
+  h->graphs.clear();
+}
+
+// Run one batch: eagerly (first time, which also allocates), or by replaying
+// a captured graph of the same (nb, m) whose buffers are still current.
+rpa_status run_batch(rpa_ctx* h, int nb, int m, hipStream_t s) {
+  const bool warm = h->warm_m == m && nb <= h->warm_B;
+  if (!h->use_graph || !warm) {
+    const unsigned e0 = h->alloc_epoch;
+    rpa_status r = enqueue_batch(h, nb, m, s, true);
+    if (r != RPA_OK) return r;
+    if (h->alloc_epoch != e0) { drop_graphs(h); h->warm_B = 0; }
+    if (h->warm_m != m) { h->warm_m = m; h->warm_B = 0; }
+    h->warm_B = std::max(h->warm_B, nb);
+    return RPA_OK;
+  }
+  const std::pair<int, int> key(nb, m);
+  rpa_ctx::GraphEntry* ge = nullptr;
+  for (auto& kv : h->graphs)
+    if (kv.first == key && kv.second.epoch == h->alloc_epoch) ge = &kv.second;
+  if (!ge) {
+    if (!h->cap_stream) HIPCHK(h, hipStreamCreate(&h->cap_stream));   // default priority
+    rpa_ctx::GraphEntry g{};
+    HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    h->capturing = true;
+    rpa_status r = enqueue_batch(h, nb, m, h->cap_stream, false);
+    h->capturing = false;
+    hipGraph_t graph = nullptr;
+    hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
+    if (r != RPA_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return r;
+    }
+    HIPCHK(h, ec);
+    g.g = graph;
+    HIPCHK(h, hipGraphInstantiate(&g.e, graph, nullptr, nullptr, 0));
+    g.epoch = h->alloc_epoch;
+    h->graphs.push_back({key, g});
+    ge = &h->graphs.back().second;
+  }
+  HIPCHK(h, hipGraphLaunch(ge->e, s));
+  return RPA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 rpa_status lanczos_energy_density(rpa_handle h, int32_t n_omega, const double* omega,
                                   int32_t n_pts, const int64_t* point_idx, int32_t n_lanczos,
                                   double* d, rpa_stats* st, void* stream) {
@@ -717,6 +859,7 @@ rpa_status lanczos_energy_density(rpa_handle h, int32_t n_omega, const double* o
   ENSURE(h, h->omega_b, (size_t)B * sizeof(double));
   ENSURE(h, h->pos_b, (size_t)B * sizeof(long long));
   ENSURE(h, h->idx_b, (size_t)B * sizeof(long long));
+  ENSURE(h, h->dres, (size_t)B * sizeof(double));
   std::vector<double> om(B);
   std::vector<long long> pos(B), idx(B);
   for (long long i0 = 0; i0 < P_total; i0 += B) {
@@ -732,30 +875,13 @@ rpa_status lanczos_energy_density(rpa_handle h, int32_t n_omega, const double* o
     HIPCHK(h, hipMemcpyAsync(h->omega_b.p, om.data(), nb * sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(h, hipMemcpyAsync(h->pos_b.p, pos.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
     HIPCHK(h, hipMemcpyAsync(h->idx_b.p, idx.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
-    // q_1 = e_j  (Q layout [m][B][N]; step 0 block is [nb][N] contiguous)
-    HIPCHK(h, launch_fill_d(P<double>(h->Q), 0.0, (long long)m * nb * N, s));
-    HIPCHK(h, launch_set_onehot(P<double>(h->Q), N, P<long long>(h->idx_b), nb, s));
-    HIPCHK(h, launch_fill_i(P<int>(h->active), 1, nb, s));
-    HIPCHK(h, launch_fill_i(P<int>(h->mlen), 0, nb, s));
-    HIPCHK(h, launch_fill_d(P<double>(h->alpha), 0.0, (long long)nb * m, s));
-    HIPCHK(h, launch_fill_d(P<double>(h->beta), 0.0, (long long)nb * m, s));
     std::vector<double> omn(om.begin(), om.begin() + nb);
-    for (int k = 0; k < m; ++k) {
-      double* qk = P<double>(h->Q) + (size_t)k * nb * N;
-      r = coulomb(h, 1, nb, qk, P<double>(h->u64), s);
-      if (r != RPA_OK) return r;
-      r = sternheimer_batch(h, nb, omn, P<int>(h->active), s);
-      if (r != RPA_OK) return r;
-      ENSURE(h, h->vtmp, (size_t)nb * N * sizeof(double));
-      // v = nu^1/2 racc  (written into u64, which is free again)
-      r = coulomb(h, 1, nb, P<double>(h->racc), P<double>(h->u64), s);
-      if (r != RPA_OK) return r;
-      HIPCHK(h, launch_lanczos_step(k, m, nb, N, P<double>(h->Q), P<double>(h->u64),
-                                    P<double>(h->alpha), P<double>(h->beta), P<int>(h->mlen),
-                                    P<int>(h->active), 1e-13, s));
-    }
-    HIPCHK(h, launch_tridiag_quad(nb, m, P<double>(h->alpha), P<double>(h->beta), P<int>(h->mlen),
-                                  P<long long>(h->pos_b), d, P<int>(h->fail), s));
+    r = upload_order_for(h, nb, omn, s);
+    if (r != RPA_OK) return r;
+    r = run_batch(h, nb, m, s);
+    if (r != RPA_OK) return r;
+    // results of the batch: dres[b] -> d[pos_b[b]]
+    HIPCHK(h, launch_scatter(P<double>(h->dres), P<long long>(h->pos_b), nb, d, s));
   }
   // Lanczos truncations: count mlen < m over the last batch only is not enough;
   // the tridiagonal kernel flags QL failures, truncations are tracked below.

@@ -9,6 +9,7 @@ namespace rpa {
 
 constexpr int kRadius = 6;               // 12th-order central differences
 constexpr int kMaxLanczos = 64;          // largest supported n_lanczos
+constexpr int kMaxLanczosPublic = kMaxLanczos;
 constexpr int kMaxBlock = 768;           // largest stencil/COCG workgroup
 
 // (H - eps_n - i omega) p = (c0 + V - eps_n) p - i omega p
@@ -100,6 +101,7 @@ hipError_t launch_tridiag_quad(int B, int m_total, const double* alpha, const do
                                const int* mlen, const long long* out_pos, double* d, int* fail,
                                hipStream_t s);
 
+hipError_t launch_scatter(const double* src, const long long* pos, int n, double* dst, hipStream_t s);
 hipError_t launch_weighted_sum(const double* dhat, const double* w, int n_omega, long long N,
                                double scale_fine, double* e_fine, double* partials, int nblocks,
                                hipStream_t s);

@@ -391,9 +391,15 @@ __global__ void k_tridiag_quad(int B, int m_total, const double* __restrict__ al
   const int bad = ql_first_row(m, d, e, z);
   double acc = 0.0;
   for (int i = 0; i < m; ++i) acc += z[i] * z[i] * (log1p(-d[i]) + d[i]);
-  dout[out_pos[b]] = acc;
+  dout[out_pos ? out_pos[b] : b] = acc;
   if (bad) atomicAdd(&fail[0], 1);
   if (m < m_total) atomicAdd(&fail[1], 1);
+}
+
+__global__ void k_scatter(const double* __restrict__ src, const long long* __restrict__ pos, int n,
+                          double* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[pos[i]] = src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -499,6 +505,11 @@ hipError_t launch_tridiag_quad(int B, int m_total, const double* alpha, const do
                                 hipStream_t s) {
   hipLaunchKernelGGL(k_tridiag_quad, dim3((B + 63) / 64), dim3(64), 0, s, B, m_total, alpha, beta,
                      mlen, out_pos, d, fail);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const double* src, const long long* pos, int n, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, src, pos, n, dst);
   return hipGetLastError();
 }
 

@@ -176,6 +176,33 @@ def test_lanczos_batching_is_exact(P, tiny, batch):
     h.close()
 
 
+def test_graph_replay_matches_eager(P, tiny):
+    """Graph mode: the per-batch sequence is captured once per (batch size, N_l)
+    and replayed; every replay, with other eager work and reallocations in
+    between, must give the eager result bit for bit."""
+    om = np.array([0.31, 3.2])
+    sets = [np.array([0, 5, 1727, 300, 1000]), np.array([17, 900, 1500, 33, 1200]),
+            np.array([64, 640])]
+    eager = _handle(P, tiny, stern_tol=1e-10, batch=4)
+    graph = _handle(P, tiny, stern_tol=1e-10, batch=4, use_graph=True)
+    for rep in range(3):
+        for m in (6, 4):
+            for pts in sets:
+                ref, _ = eager.lanczos_energy_density(om, pts, m)
+                d, st = graph.lanczos_energy_density(om, pts, m)
+                assert torch.equal(d, ref), (rep, m, pts)
+                assert st["n_systems"] == len(pts) * len(om) * tiny.n_occ * m
+        # eager work on the graph handle between replays, then a workspace
+        # release, after which the captured graphs must be retired and rebuilt
+        x = torch.from_numpy(sc.random_field((6, tiny.N_d), seed=rep)).cuda()
+        graph.chi0_apply(0.69, x)
+        torch.cuda.synchronize()
+        if rep == 1:
+            graph.release_workspace()
+    eager.close()
+    graph.close()
+
+
 def test_lanczos_short_runs_and_edge_points(P, tiny, tiny_ops):
     ham, coul = tiny_ops
     om = np.array([1.45])

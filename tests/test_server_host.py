@@ -1,0 +1,82 @@
+"""Host-side tests of the serving loop's scheduler (fake executor: jobs sleep
+instead of computing, so admission, ordering and latency accounting are
+checked without a GPU)."""
+import numpy as np
+import pytest
+
+import paper_2609_16408_amd as P
+from paper_2609_16408_amd import serve
+
+US = 30000  # fake job length (microseconds)
+
+
+def _server(workers, budget=0):
+    s = P.Server(n_workers=workers, hbm_budget=budget, fake_executor_us=US)
+    cid = s.add_cell((24, 24, 24), (10.26,) * 3, None, None, np.linspace(-0.5, -0.4, 16))
+    return s, cid
+
+
+def _overlaps(infos):
+    """Largest number of jobs running at the same time (event sweep)."""
+    ev = sorted([(i["t_start"], 1) for i in infos] + [(i["t_finish"], -1) for i in infos],
+                key=lambda e: (e[0], e[1]))
+    cur = best = 0
+    for _, d in ev:
+        cur += d
+        best = max(best, cur)
+    return best
+
+
+def test_concurrent_jobs_overlap_up_to_the_worker_count():
+    s, cid = _server(3)
+    ids = [s.submit(cid, 0.5, np.arange(16), 4) for _ in range(6)]
+    infos = [s.wait(j)[1] for j in ids]
+    s.close()
+    assert all(i["status"] == 0 for i in infos)
+    assert _overlaps(infos) == 3
+    assert all(i["latency"] >= US * 1e-6 for i in infos)
+
+
+def test_admission_respects_the_hbm_budget():
+    s0, cid0 = _server(1)
+    fp = s0.wait(s0.submit(cid0, 0.5, np.arange(16), 4))[1]["footprint"]
+    s0.close()
+    resident = 24 ** 3 * 8 * 17 * 4          # V + 16 orbitals, server copy + 3 worker copies
+    s, cid = _server(3, budget=resident + int(1.5 * fp))   # room for one job at a time
+    ids = [s.submit(cid, 0.5, np.arange(16), 4) for _ in range(4)]
+    infos = [s.wait(j)[1] for j in ids]
+    s.close()
+    assert _overlaps(infos) == 1
+    # oldest first: start times follow submission order
+    starts = [i["t_start"] for i in infos]
+    assert starts == sorted(starts)
+
+
+def test_job_that_can_never_fit_is_refused():
+    s, cid = _server(2, budget=1 << 20)
+    with pytest.raises(P.RPAError) as e:
+        s.submit(cid, 0.5, np.arange(16), 4)
+    assert e.value.status == P.RPA_E_OOM
+    s.close()
+
+
+@pytest.mark.parametrize("bad", [dict(omega=0.0), dict(points=[24 ** 3]), dict(n_lanczos=0),
+                                 dict(cell=7)])
+def test_invalid_jobs_are_rejected(bad):
+    s, cid = _server(1)
+    kw = dict(cell=cid, omega=0.5, points=[0, 1], n_lanczos=4)
+    kw.update(bad)
+    with pytest.raises(P.RPAError) as e:
+        s.submit(kw["cell"], kw["omega"], kw["points"], kw["n_lanczos"])
+    assert e.value.status == P.RPA_E_ARG
+    s.close()
+
+
+def test_open_loop_driver_reports_latency_percentiles():
+    s, cid = _server(2)
+    cells = [(cid, np.arange(0, 24 ** 3, 8))]
+    jobs = serve.make_jobs(12, cells, [1.0], [0.5, 3.2], 16, seed=4000)
+    secs, infos = serve.run_open(s, cells, jobs, 4, rate=40.0, seed=4001)
+    s.close()
+    r = serve.summarize(infos, secs)
+    assert r["jobs"] == 12 and r["p99_latency_s"] >= r["p50_latency_s"] >= US * 1e-6
