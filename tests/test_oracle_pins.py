@@ -157,6 +157,58 @@ def test_synthcell_orbitals_are_eigenpairs_of_oracle_H(tiny_cell, tiny_ops, tiny
     assert np.allclose(c.eps, ev[: c.n_occ], atol=1e-10)
 
 
+# --- nonlocal projectors (separable V_nl of the Background section) -------------
+
+@pytest.fixture(scope="module")
+def nl_cell():
+    import synthcell
+    return synthcell.preset("tiny", with_projectors=True, proj_seed=201)
+
+
+def _single_projector(proj, p):
+    a, b = int(proj["ptr"][p]), int(proj["ptr"][p + 1])
+    return {"ptr": np.array([0, b - a]), "idx": proj["idx"][a:b], "val": proj["val"][a:b],
+            "gamma": proj["gamma"][p:p + 1]}
+
+
+def test_nonlocal_single_projector_closed_form(nl_cell):
+    """One projector chi (h^3 |chi|^2 = 1): V_nl chi = gamma chi, V_nl x = 0 for x _|_ chi."""
+    c = nl_cell
+    h0 = O.Hamiltonian(c.n, c.L, c.v_loc)
+    rng = np.random.default_rng(5)
+    for p in (0, 3, 17, c.proj["gamma"].size - 1):
+        one = _single_projector(c.proj, p)
+        h1 = O.Hamiltonian(c.n, c.L, c.v_loc, proj=one)
+        chi = np.zeros(c.N_d)
+        np.add.at(chi, one["idx"], one["val"])
+        assert abs(c.dV * chi @ chi - 1.0) < 1e-12
+        y = h1.apply(chi) - h0.apply(chi)
+        assert np.abs(y - one["gamma"][0] * chi).max() < 1e-12 * np.abs(chi).max()
+        x = rng.standard_normal(c.N_d)
+        x -= (c.dV * chi @ x) * chi
+        assert np.abs(h1.apply(x) - h0.apply(x)).max() < 1e-12 * np.abs(x).max()
+
+
+def test_nonlocal_trace_rank_and_sign(nl_cell):
+    """tr V_nl = sum gamma (unit-norm projectors); V_nl is PSD of rank n_proj."""
+    c = nl_cell
+    Vnl = O.Hamiltonian(c.n, c.L, c.v_loc, proj=c.proj).dense() - O.Hamiltonian(c.n, c.L, c.v_loc).dense()
+    g = c.proj["gamma"]
+    assert abs(np.trace(Vnl) - g.sum()) < 1e-10 * g.sum()
+    lam = np.linalg.eigvalsh(Vnl)
+    assert lam.min() > -1e-12 * lam.max()
+    assert int((lam > 1e-9 * lam.max()).sum()) == g.size
+
+
+def test_synthcell_orbitals_with_projectors_are_eigenpairs_of_oracle_H(nl_cell):
+    c = nl_cell
+    ham = O.Hamiltonian(c.n, c.L, c.v_loc, proj=c.proj)
+    R = ham.apply(c.psi.T).T - c.eps[:, None] * c.psi
+    assert np.abs(R).max() * math.sqrt(c.dV) < 1e-9
+    ev = np.linalg.eigvalsh(ham.dense())
+    assert np.allclose(c.eps, ev[: c.n_occ], atol=1e-10)
+
+
 @pytest.mark.parametrize("omega", [0.0203, 0.69, 49.37])
 def test_sternheimer_chi0_equals_sum_over_states(tiny_cell, tiny_ops, tiny_dense, omega):
     c = tiny_cell
