@@ -159,7 +159,7 @@ class Handle:
 
     def __init__(self, n, L, v_loc, psi, eps, precision="fp64", stern_tol=1e-10,
                  stern_maxit=20000, batch=0, tile_y=0, slots_per_cu=0, inner_tol=0.0,
-                 hbm_budget=0, use_graph=False, stream=None):
+                 hbm_budget=0, use_graph=False, proj=None, stream=None):
         import torch
         self._torch = torch
         dev = torch.device("cuda")
@@ -181,7 +181,7 @@ class Handle:
         prm.v_loc = v.data_ptr()
         prm.psi = p.data_ptr()
         prm.eps = self.eps.ctypes.data
-        prm.n_proj = 0
+        keep = _set_proj(prm, proj)   # host arrays, copied by rpa_setup
         prm.precision = PRECISION[precision]
         prm.stern_tol = float(stern_tol)
         prm.stern_maxit = int(stern_maxit)
@@ -193,6 +193,7 @@ class Handle:
         prm.use_graph = 1 if use_graph else 0
         h = ctypes.c_void_p()
         _check(lib().rpa_setup(ctypes.byref(prm), _stream(stream), ctypes.byref(h)), "rpa_setup")
+        del keep
         self._h = h
         self.precision = precision
 
@@ -299,6 +300,23 @@ class Handle:
                 "block": block.value, "tile_y": ty.value}
 
 
+def _set_proj(prm, proj):
+    """Fill the projector fields of SetupParams from a dict with CSR arrays
+    'ptr', 'idx', 'val', 'gamma' (None: no projectors); returns the arrays,
+    which must stay alive until the C call that reads them returns."""
+    if proj is None:
+        prm.n_proj = 0
+        return ()
+    ptr = np.ascontiguousarray(proj["ptr"], dtype=np.int64)
+    idx = np.ascontiguousarray(proj["idx"], dtype=np.int64)
+    val = np.ascontiguousarray(proj["val"], dtype=np.float64)
+    gam = np.ascontiguousarray(proj["gamma"], dtype=np.float64)
+    prm.n_proj = int(ptr.size - 1)
+    prm.proj_ptr, prm.proj_idx = ptr.ctypes.data, idx.ctypes.data
+    prm.proj_val, prm.proj_gamma = val.ctypes.data, gam.ctypes.data
+    return (ptr, idx, val, gam)
+
+
 def _setup_params(n, L, v_ptr, psi_ptr, eps, precision, stern_tol, stern_maxit, batch=0,
                   tile_y=0, slots_per_cu=0, inner_tol=0.0, hbm_budget=0):
     prm = SetupParams()
@@ -334,7 +352,7 @@ class Server:
         self._out = {}
 
     def add_cell(self, n, L, v_loc, psi, eps, precision="fp32_refine", stern_tol=1e-6,
-                 stern_maxit=20000, batch=0):
+                 stern_maxit=20000, batch=0, proj=None):
         eps = np.ascontiguousarray(eps, dtype=np.float64)
         if self.fake:
             prm = _setup_params(n, L, None, None, eps, precision, stern_tol, stern_maxit, batch)
@@ -344,9 +362,11 @@ class Server:
             p = torch.as_tensor(np.ascontiguousarray(psi, dtype=np.float64)).cuda()
             prm = _setup_params(n, L, v.data_ptr(), p.data_ptr(), eps, precision, stern_tol,
                                 stern_maxit, batch)
+        keep = _set_proj(prm, proj)   # copied by rpa_server_add_cell
         cid = ctypes.c_int32()
         _check(lib().rpa_server_add_cell(self._h, ctypes.byref(prm), ctypes.byref(cid)),
                "rpa_server_add_cell")
+        del keep
         self._keep[cid.value] = eps
         return cid.value
 
@@ -391,4 +411,5 @@ class Server:
 
 def handle_for_cell(cell, **kw) -> Handle:
     """Handle for a synthcell.Cell (convenience for tests and the benchmark)."""
+    kw.setdefault("proj", cell.proj)
     return Handle(cell.n, cell.L, cell.v_loc, cell.psi, cell.eps, **kw)

@@ -89,6 +89,87 @@ __device__ __forceinline__ void block_reduce(double (&v)[K], double* red) {
   __syncthreads();
 }
 
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ const T* nl_pick(const float* a, const double* b) {
+  if constexpr (sizeof(T) == 4) return a;
+  else return b;
+}
+
+// Nonlocal projections of one vector x (Background section, separable V_nl):
+// c_p = chi_p^T x for every projector.  Each wave takes whole support groups
+// (the projectors of a group share their support, so x is gathered once per
+// group); lane 0 stores w_p = gamma_p h^3 c_p into coef (LDS) and adds
+// sum_p w_p c_p = x^T V_nl x (unconjugated) to mu.  The caller synchronises
+// before coef is read.
+template <typename T, typename XT>
+__device__ void nl_project(const NlArgs& nl, const typename V2<XT>::t* x,
+                           typename V2<T>::t* coef, double& mu_re, double& mu_im) {
+  const int lane = threadIdx.x & 63;
+  const int wave = uni((int)(threadIdx.x >> 6));
+  const int nw = (int)(blockDim.x >> 6);
+  const T* bv = nl_pick<T>(nl.bv32, nl.bv64);
+  for (int gi = wave; gi < nl.n_groups; gi += nw) {
+    const int4 G = nl.ginfo[gi];
+    const int s0 = uni(G.x), S = uni(G.y) - s0, p0 = uni(G.z), np = uni(G.w);
+    const T* val = bv + uni(nl.gvoff[gi]);
+    const int* idx = nl.bidx + s0;
+    T ar[kMaxGroup], ai[kMaxGroup];
+#pragma unroll
+    for (int k = 0; k < kMaxGroup; ++k) { ar[k] = 0; ai[k] = 0; }
+    for (int j = lane; j < S; j += 64) {
+      const typename V2<XT>::t v = x[idx[j]];
+      const T vr = (T)v.x, vi = (T)v.y;
+#pragma unroll
+      for (int k = 0; k < kMaxGroup; ++k) {
+        if (k < np) {
+          const T c = val[k * S + j];
+          ar[k] += c * vr;
+          ai[k] += c * vi;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxGroup; ++k) {
+      if (k < np) {
+        ar[k] = wave_sum(ar[k]);
+        ai[k] = wave_sum(ai[k]);
+        if (lane == 0) {
+          const double gd = nl.gdv[p0 + k];
+          const double cr = (double)ar[k], ci = (double)ai[k];
+          const double wr = gd * cr, wi = gd * ci;
+          typename V2<T>::t w;
+          w.x = (T)wr;
+          w.y = (T)wi;
+          coef[p0 + k] = w;
+          mu_re += wr * cr - wi * ci;
+          mu_im += wr * ci + wi * cr;
+        }
+      }
+    }
+  }
+}
+
+// (V_nl x)_i = sum over the entries of point i of w_p chi_p(i), added to (ar, ai).
+template <typename T>
+__device__ __forceinline__ void nl_point(const int* pm_ptr, const int* pm_proj, const T* pm_v,
+                                         const typename V2<T>::t* coef, long long i, T& ar,
+                                         T& ai) {
+  const int e1 = pm_ptr[i + 1];
+  for (int e = pm_ptr[i]; e < e1; ++e) {
+    const T c = pm_v[e];
+    const typename V2<T>::t w = coef[pm_proj[e]];
+    ar += c * w.x;
+    ai += c * w.y;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // x-marching stencil sweep over all tiles of one system.
 //
@@ -384,6 +465,12 @@ __host__ __device__ inline size_t lds_plane_bytes(const Geom& g, int pitch, bool
   return (b + 255) & ~(size_t)255;
 }
 
+// Bytes of LDS for the reductions (4 doubles per wave plus the result).
+__host__ __device__ inline size_t red_bytes(int block) {
+  const size_t nw = (size_t)(block + 63) / 64;
+  return ((nw + 1) * 4 * sizeof(double) + 255) & ~(size_t)255;
+}
+
 // ---------------------------------------------------------------------------
 // Policies
 
@@ -398,6 +485,11 @@ struct ResidPol {
   TI2* r;
   double c0, eps, om;
   double rr, bb, rho_re, rho_im;
+  bool nl_on;                     // nonlocal term present
+  const int* pm_ptr;              // point-major projector entries
+  const int* pm_proj;
+  const double* pm_v;
+  const double2* coef;            // w_p of x (LDS)
   static constexpr int kPF = 1;   // runs a few times per solve: keep registers low
   struct Aux { double v, b; };
   __device__ double2 load(size_t po, int c) const { return (x + po)[c]; }
@@ -409,8 +501,9 @@ struct ResidPol {
   }
   __device__ void center(size_t po, int c, double2 xv, double2 nb, const Aux& ax) {
     const double a = c0 + ax.v - eps;
-    const double axr = a * xv.x + om * xv.y + nb.x;
-    const double axi = a * xv.y - om * xv.x + nb.y;
+    double axr = a * xv.x + om * xv.y + nb.x;
+    double axi = a * xv.y - om * xv.x + nb.y;
+    if (nl_on) nl_point<double>(pm_ptr, pm_proj, pm_v, coef, (long long)po + c, axr, axi);
     const double bval = ax.b;
     const double rx = bval - axr;
     const double ry = -axi;
@@ -485,17 +578,29 @@ struct HPol {
 // ---------------------------------------------------------------------------
 // Streaming passes of one system (whole workgroup).
 
+// Point-major nonlocal entries and the coefficients w_p of p (null: none).
+template <typename T>
+struct NlPoint {
+  const int* ptr;
+  const int* proj;
+  const T* v;
+  const typename V2<T>::t* coef;
+};
+
 // x (XT) = first ? alpha p : x + alpha p;  r -= alpha q;  returns ||r||^2, r^T r.
+// With a nonlocal term, q holds (H_loc - sigma) p and V_nl p is added here.
 // Four elements per thread per trip, all loads issued before the arithmetic.
 template <typename T, typename XT>
 __device__ __forceinline__ void update_sweep(long long N, typename V2<XT>::t* x,
                                              const typename V2<T>::t* p, typename V2<T>::t* r,
                                              const typename V2<T>::t* q, T ar, T ai, bool first,
-                                             double& rr, double& rho_re, double& rho_im) {
+                                             const NlPoint<T>& nl, double& rr, double& rho_re,
+                                             double& rho_im) {
   typedef typename V2<T>::t T2;
   typedef typename V2<XT>::t X2;
   constexpr int U = 4;
   const long long st = blockDim.x;
+  const bool nl_on = nl.coef != nullptr;
   long long i0 = threadIdx.x;
   for (; i0 + (U - 1) * st < N; i0 += U * st) {
     T2 pv[U], qv[U], rv[U];
@@ -507,6 +612,11 @@ __device__ __forceinline__ void update_sweep(long long N, typename V2<XT>::t* x,
       qv[u] = q[i];
       rv[u] = r[i];
       if (!first) xv[u] = x[i];
+    }
+    if (nl_on) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        nl_point<T>(nl.ptr, nl.proj, nl.v, nl.coef, i0 + u * st, qv[u].x, qv[u].y);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -527,8 +637,9 @@ __device__ __forceinline__ void update_sweep(long long N, typename V2<XT>::t* x,
   }
   for (long long i = i0; i < N; i += st) {
     const T2 pv = p[i];
-    const T2 qv = q[i];
+    T2 qv = q[i];
     T2 rv = r[i];
+    if (nl_on) nl_point<T>(nl.ptr, nl.proj, nl.v, nl.coef, i, qv.x, qv.y);
     const T dx = ar * pv.x - ai * pv.y;
     const T dy = ar * pv.y + ai * pv.x;
     X2 xv;
@@ -580,7 +691,7 @@ __device__ __forceinline__ void record(const CocgArgs& a, int s, int its, int cy
 // ---------------------------------------------------------------------------
 // One system, FP64 throughout.
 template <bool FULL, int HS, int PITCH>
-__device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red) {
+__device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red, char* nlc) {
   const Geom& g = a.g;
   const long long N = g.N;
   const int b = s / a.n_occ;
@@ -595,10 +706,21 @@ __device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red) {
   const double eps = a.eps[n];
   const double om = a.omega[b];
 
+  const bool nl_on = a.nl.n_proj > 0;
+  double2* coef = reinterpret_cast<double2*>(nlc);
+  NlPoint<double> nlp{a.nl.pm_ptr, a.nl.pm_proj, a.nl.pm_v64, nl_on ? coef : nullptr};
+
   ResidPol<double> rp;
   rp.x = x; rp.v = a.v64; rp.psi = a.psi64 + (size_t)n * N; rp.u = a.u64 + (size_t)b * N;
   rp.r = r; rp.c0 = a.c64.c0; rp.eps = eps; rp.om = om;
   rp.rr = rp.bb = rp.rho_re = rp.rho_im = 0.0;
+  rp.nl_on = nl_on; rp.pm_ptr = a.nl.pm_ptr; rp.pm_proj = a.nl.pm_proj; rp.pm_v = a.nl.pm_v64;
+  rp.coef = coef;
+  if (nl_on) {
+    double d0 = 0.0, d1 = 0.0;
+    nl_project<double, double>(a.nl, x, coef, d0, d1);
+    __syncthreads();
+  }
   march_light<double, FULL, HS>(g, a.c64, rp, lds, 0, g.ntiles);
   double v4[4] = {rp.rr, rp.bb, rp.rho_re, rp.rho_im};
   block_reduce<4>(v4, red);
@@ -622,12 +744,13 @@ __device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red) {
       ap.mu_re = ap.mu_im = 0.0;
       march<double, FULL, HS, PITCH>(g, a.c64, ap, lds, 0, g.ntiles);
       double m2[2] = {ap.mu_re, ap.mu_im};
+      if (nl_on) nl_project<double, double>(a.nl, pnew, coef, m2[0], m2[1]);
       block_reduce<2>(m2, red);
       if (fabs(m2[0]) + fabs(m2[1]) < 1e-300) { status = 2; break; }
       double al_r, al_i;
       cdiv(rho_r, rho_i, m2[0], m2[1], al_r, al_i);
       double rr = 0.0, nr = 0.0, ni = 0.0;
-      update_sweep<double, double>(N, x, pnew, r, q, al_r, al_i, false, rr, nr, ni);
+      update_sweep<double, double>(N, x, pnew, r, q, al_r, al_i, false, nlp, rr, nr, ni);
       double u3[3] = {rr, nr, ni};
       block_reduce<3>(u3, red);
       ++its;
@@ -649,7 +772,7 @@ __device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red) {
 // replaced by the true FP64 residual b - A x64.  Convergence is declared on
 // the FP64 residual only.
 template <bool FULL, int HS, int PITCH>
-__device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red) {
+__device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, char* nlc) {
   const Geom& g = a.g;
   const long long N = g.N;
   const int b = s / a.n_occ;
@@ -664,10 +787,24 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red) 
   const double eps = a.eps[n];
   const double om = a.omega[b];
 
+  // nonlocal coefficients: FP64 for the residual sweeps, FP32 for the inner
+  // iterations (same LDS region, never live at the same time)
+  const bool nl_on = a.nl.n_proj > 0;
+  double2* coef64 = reinterpret_cast<double2*>(nlc);
+  float2* coef32 = reinterpret_cast<float2*>(nlc);
+  NlPoint<float> nlp{a.nl.pm_ptr, a.nl.pm_proj, a.nl.pm_v32, nl_on ? coef32 : nullptr};
+
   ResidPol<float> rp;
   rp.x = x; rp.v = a.v64; rp.psi = a.psi64 + (size_t)n * N; rp.u = a.u64 + (size_t)b * N;
   rp.r = r; rp.c0 = a.c64.c0; rp.eps = eps; rp.om = om;
   rp.rr = rp.bb = rp.rho_re = rp.rho_im = 0.0;
+  rp.nl_on = nl_on; rp.pm_ptr = a.nl.pm_ptr; rp.pm_proj = a.nl.pm_proj; rp.pm_v = a.nl.pm_v64;
+  rp.coef = coef64;
+  if (nl_on) {
+    double d0 = 0.0, d1 = 0.0;
+    nl_project<double, double>(a.nl, x, coef64, d0, d1);
+    __syncthreads();
+  }
   march_light<double, FULL, HS>(g, a.c64, rp, reinterpret_cast<double2*>(smem), 0, g.ntiles);
   double v4[4] = {rp.rr, rp.bb, rp.rho_re, rp.rho_im};
   block_reduce<4>(v4, red);
@@ -698,12 +835,14 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red) 
       ap.mu_re = ap.mu_im = 0.0;
       march<float, FULL, HS, PITCH>(g, a.c32, ap, reinterpret_cast<float2*>(smem), 0, g.ntiles);
       double m2[2] = {ap.mu_re, ap.mu_im};
+      if (nl_on) nl_project<float, float>(a.nl, pnew, coef32, m2[0], m2[1]);
       block_reduce<2>(m2, red);
       if (fabs(m2[0]) + fabs(m2[1]) < 1e-300) { status = 2; break; }
       double al_r, al_i;
       cdiv(rho_r, rho_i, m2[0], m2[1], al_r, al_i);
       double rr = 0.0, nr = 0.0, ni = 0.0;
-      update_sweep<float, float>(N, d, pnew, r, q, (float)al_r, (float)al_i, dfresh, rr, nr, ni);
+      update_sweep<float, float>(N, d, pnew, r, q, (float)al_r, (float)al_i, dfresh, nlp, rr, nr,
+                                 ni);
       double u3[3] = {rr, nr, ni};
       block_reduce<3>(u3, red);
       ++its;
@@ -718,6 +857,11 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red) 
         ++updates;
         last_upd = its;
         rp.rr = rp.bb = rp.rho_re = rp.rho_im = 0.0;
+        if (nl_on) {
+          double d0 = 0.0, d1 = 0.0;
+          nl_project<double, double>(a.nl, x, coef64, d0, d1);
+          __syncthreads();
+        }
         march_light<double, FULL, HS>(g, a.c64, rp, reinterpret_cast<double2*>(smem), 0, g.ntiles);
         double w4[4] = {rp.rr, rp.bb, rp.rho_re, rp.rho_im};
         block_reduce<4>(w4, red);
@@ -753,6 +897,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_cocg(CocgArgs a) {
   char* smem = reinterpret_cast<char*>(smem_d);
   const Geom& g = a.g;
   double* red = reinterpret_cast<double*>(smem + lds_plane_bytes(g, PITCH, REFINE));
+  char* nlc = smem + lds_plane_bytes(g, PITCH, REFINE) + red_bytes(blockDim.x);
   __shared__ int s_item;
   int item = 0;
   if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
@@ -764,8 +909,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_cocg(CocgArgs a) {
     const int b = s / a.n_occ;
     const int live = a.active == nullptr ? 1 : uni(a.active[b]);
     if (live) {
-      if (REFINE) solve_refine<FULL, HS, PITCH>(a, s, smem, red);
-      else solve_fp64<FULL, HS, PITCH>(a, s, smem, red);
+      if (REFINE) solve_refine<FULL, HS, PITCH>(a, s, smem, red, nlc);
+      else solve_fp64<FULL, HS, PITCH>(a, s, smem, red, nlc);
     } else if (threadIdx.x == 0) {
       a.out_iters[s] = 0;
       a.out_cycles[s] = 0;
@@ -796,6 +941,36 @@ __global__ void __launch_bounds__(kMaxBlock) k_happly(Geom g, StencilCoef<T> cf,
   march<T, FULL, HS, PITCH>(g, cf, p, reinterpret_cast<T2*>(smem_d), blockIdx.x, blockIdx.x + 1);
 }
 
+// Nonlocal term of the plain operator application: per vector, the
+// projections (one workgroup each, coefficients through LDS to coef), then
+// y += V_nl x point by point.
+template <typename T>
+__global__ void __launch_bounds__(256) k_nl_coef(NlArgs nl, const void* x, long long N,
+                                                  void* coef) {
+  typedef typename V2<T>::t T2;
+  extern __shared__ double smem_d[];
+  T2* c = reinterpret_cast<T2*>(smem_d);
+  const T2* xv = reinterpret_cast<const T2*>(x) + (size_t)blockIdx.x * N;
+  double d0 = 0.0, d1 = 0.0;
+  nl_project<T, T>(nl, xv, c, d0, d1);
+  __syncthreads();
+  T2* out = reinterpret_cast<T2*>(coef) + (size_t)blockIdx.x * nl.n_proj;
+  for (int p = threadIdx.x; p < nl.n_proj; p += blockDim.x) out[p] = c[p];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_nl_add(NlArgs nl, long long N, const void* coef,
+                                                 void* y) {
+  typedef typename V2<T>::t T2;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const T2* c = reinterpret_cast<const T2*>(coef) + (size_t)blockIdx.y * nl.n_proj;
+  T2* yv = reinterpret_cast<T2*>(y) + (size_t)blockIdx.y * N;
+  T2 o = yv[i];
+  nl_point<T>(nl.pm_ptr, nl.pm_proj, nl_pick<T>(nl.pm_v32, nl.pm_v64), c, i, o.x, o.y);
+  yv[i] = o;
+}
+
 }  // namespace
 
 namespace {
@@ -820,13 +995,13 @@ const void* cocg_fn(int m, int pitch) {
 
 bool geom_supported(const Geom& g) { return g.nz + 2 * R <= 128; }
 
-size_t cocg_shmem_bytes(const Geom& g, int block, bool fp32_refine) {
-  const int nw = (block + 63) / 64;
-  return lds_plane_bytes(g, pitch_for(g), fp32_refine) + (size_t)(nw + 1) * 4 * sizeof(double);
+size_t cocg_shmem_bytes(const Geom& g, int block, bool fp32_refine, int n_proj) {
+  return lds_plane_bytes(g, pitch_for(g), fp32_refine) + red_bytes(block) +
+         (size_t)n_proj * sizeof(double2);
 }
 
-int cocg_blocks_per_cu(const Geom& g, int block, bool fp32_refine) {
-  const size_t shmem = cocg_shmem_bytes(g, block, fp32_refine);
+int cocg_blocks_per_cu(const Geom& g, int block, bool fp32_refine, int n_proj) {
+  const size_t shmem = cocg_shmem_bytes(g, block, fp32_refine, n_proj);
   const int m = tile_mode(g, block);
   int nb = 0;
   const void* fn = fp32_refine ? cocg_fn<true>(m, pitch_for(g)) : cocg_fn<false>(m, pitch_for(g));
@@ -893,10 +1068,25 @@ hipError_t launch_happly(const Geom& g, const StencilCoef<double>& c64, const St
                          const double* v64, const float* v32, int nvec, const double* shift_re,
                          const double* shift_im, const void* x, void* y, bool fp32,
                          int block, hipStream_t s) {
-  const size_t shmem = cocg_shmem_bytes(g, block, fp32);
+  const size_t shmem = cocg_shmem_bytes(g, block, fp32, 0);
   dim3 grid(g.ntiles, nvec);
   if (fp32) return launch_ht<float>(g, c32, v32, shift_re, shift_im, x, y, grid, block, shmem, s);
   return launch_ht<double>(g, c64, v64, shift_re, shift_im, x, y, grid, block, shmem, s);
+}
+
+hipError_t launch_nl_apply(const NlArgs& nl, long long N, int nvec, const void* x, void* y,
+                           void* coef, bool fp32, hipStream_t s) {
+  if (nl.n_proj == 0) return hipSuccess;
+  const size_t shmem = (size_t)nl.n_proj * (fp32 ? sizeof(float2) : sizeof(double2));
+  const dim3 ga((unsigned)((N + 255) / 256), (unsigned)nvec);
+  if (fp32) {
+    hipLaunchKernelGGL((k_nl_coef<float>), dim3(nvec), dim3(256), shmem, s, nl, x, N, coef);
+    hipLaunchKernelGGL((k_nl_add<float>), ga, dim3(256), 0, s, nl, N, (const void*)coef, y);
+  } else {
+    hipLaunchKernelGGL((k_nl_coef<double>), dim3(nvec), dim3(256), shmem, s, nl, x, N, coef);
+    hipLaunchKernelGGL((k_nl_add<double>), ga, dim3(256), 0, s, nl, N, (const void*)coef, y);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace rpa

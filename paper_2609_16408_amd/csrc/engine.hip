@@ -10,6 +10,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 using namespace rpa;
@@ -52,6 +53,9 @@ struct rpa_ctx {
   StencilCoef<float> c32;
   Geom geom;
   int block = 0;
+  NlArgs nl{};                       // nonlocal projectors (device layouts)
+  std::vector<void*> nl_mem;         // their allocations
+  DevBuf nlcoef;                     // coefficients for the plain operator application
 
   // workspaces
   DevBuf x64, slots, u64, racc, vtmp, tmpA, Q, alpha, beta, mlen, active, order, iters, cycles,
@@ -290,7 +294,8 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
   }
   HIPCHK(h, launch_fill_i(P<int>(h->counter), 0, 1, s));
 
-  const int bpc = h->slots_per_cu > 0 ? h->slots_per_cu : cocg_blocks_per_cu(h->geom, h->block, refine);
+  const int bpc = h->slots_per_cu > 0 ? h->slots_per_cu
+                                      : cocg_blocks_per_cu(h->geom, h->block, refine, h->nl.n_proj);
   int grid = std::max(1, std::min(n_items, bpc * h->num_cu));
   const long long sb = cocg_slot_bytes(h->geom, refine);
   ENSURE(h, h->slots, (size_t)grid * sb);
@@ -322,7 +327,8 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
   a.maxit = h->maxit;
   a.inner_tol = h->inner_tol;
   a.max_cycles = 0;
-  const size_t shmem = cocg_shmem_bytes(h->geom, h->block, refine);
+  a.nl = h->nl;
+  const size_t shmem = cocg_shmem_bytes(h->geom, h->block, refine, h->nl.n_proj);
   if (timing) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     rpa_status es = cocg_events(h, &e0, &e1);
@@ -485,6 +491,80 @@ rpa_status rpa_frequency_rule(int32_t n_omega, double* omega, double* weight) {
   return RPA_OK;
 }
 
+}  // extern "C"
+namespace {
+
+// Host form of the two projector layouts (see NlArgs): groups of up to
+// kMaxGroup consecutive projectors with identical support lists, and the
+// point-major list of (projector, value) entries, both in input order.
+struct NlHost {
+  std::vector<int4> ginfo;
+  std::vector<int> gvoff, bidx, pm_ptr, pm_proj;
+  std::vector<float> bv32, pm_v32;
+  std::vector<double> bv64, pm_v64, gdv;
+};
+
+std::string nl_build(const rpa_setup_params* p, long long N, double dV, NlHost& o) {
+  const int np = p->n_proj;
+  if (np == 0) return "";
+  if (np < 0 || np > kMaxProj) return "n_proj must be in [0, 4096]";
+  if (!p->proj_ptr || !p->proj_idx || !p->proj_val || !p->proj_gamma)
+    return "proj_ptr, proj_idx, proj_val and proj_gamma are required when n_proj > 0";
+  const int64_t* ptr = p->proj_ptr;
+  if (ptr[0] != 0) return "proj_ptr[0] must be 0";
+  for (int q = 0; q < np; ++q)
+    if (ptr[q + 1] < ptr[q]) return "proj_ptr must be non-decreasing";
+  const int64_t nnz = ptr[np];
+  if (nnz > (int64_t)0x3fffffff) return "too many projector entries";
+  for (int64_t e = 0; e < nnz; ++e) {
+    if (p->proj_idx[e] < 0 || p->proj_idx[e] >= N) return "proj_idx out of range";
+    if (!std::isfinite(p->proj_val[e])) return "proj_val must be finite";
+  }
+  for (int q = 0; q < np; ++q)
+    if (!std::isfinite(p->proj_gamma[q])) return "proj_gamma must be finite";
+  for (int q = 0; q < np;) {
+    const int64_t a0 = ptr[q], S = ptr[q + 1] - a0;
+    int cnt = 1;
+    while (cnt < kMaxGroup && q + cnt < np) {
+      const int64_t b0 = ptr[q + cnt];
+      if (ptr[q + cnt + 1] - b0 != S ||
+          !std::equal(p->proj_idx + a0, p->proj_idx + a0 + S, p->proj_idx + b0))
+        break;
+      ++cnt;
+    }
+    o.ginfo.push_back(make_int4((int)o.bidx.size(), (int)(o.bidx.size() + S), q, cnt));
+    o.gvoff.push_back((int)o.bv64.size());
+    for (int64_t j = 0; j < S; ++j) o.bidx.push_back((int)p->proj_idx[a0 + j]);
+    for (int k = 0; k < cnt; ++k)
+      for (int64_t j = 0; j < S; ++j) {
+        const double v = p->proj_val[ptr[q + k] + j];
+        o.bv64.push_back(v);
+        o.bv32.push_back((float)v);
+      }
+    q += cnt;
+  }
+  o.pm_ptr.assign((size_t)N + 1, 0);
+  for (int64_t e = 0; e < nnz; ++e) ++o.pm_ptr[(size_t)p->proj_idx[e] + 1];
+  for (long long i = 0; i < N; ++i) o.pm_ptr[i + 1] += o.pm_ptr[i];
+  std::vector<int> fill(o.pm_ptr.begin(), o.pm_ptr.end() - 1);
+  o.pm_proj.resize(nnz);
+  o.pm_v64.resize(nnz);
+  o.pm_v32.resize(nnz);
+  for (int q = 0; q < np; ++q)
+    for (int64_t e = ptr[q]; e < ptr[q + 1]; ++e) {
+      const int at = fill[p->proj_idx[e]]++;
+      o.pm_proj[at] = q;
+      o.pm_v64[at] = p->proj_val[e];
+      o.pm_v32[at] = (float)p->proj_val[e];
+    }
+  o.gdv.resize(np);
+  for (int q = 0; q < np; ++q) o.gdv[q] = p->proj_gamma[q] * dV;
+  return "";
+}
+
+}  // namespace
+extern "C" {
+
 rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   ARG_CHECK(p && out, "null params or output");
   *out = nullptr;
@@ -500,7 +580,6 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   ARG_CHECK(p->stern_tol > 0 && p->stern_tol < 1, "stern_tol must be in (0, 1)");
   ARG_CHECK(p->stern_maxit > 0, "stern_maxit must be positive");
   ARG_CHECK(p->batch >= 0, "batch must be >= 0");
-  ARG_CHECK(p->n_proj == 0, "nonlocal projectors are not supported by this build");
   for (int i = 0; i < p->n_occ; ++i) ARG_CHECK(std::isfinite(p->eps[i]), "eps must be finite");
   ARG_CHECK(p->inner_tol >= 0 && p->inner_tol < 1, "inner_tol must be in [0, 1)");
   // tile rows
@@ -520,6 +599,17 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
     Geom gq;
     gq.nx = p->n[0]; gq.ny = ny; gq.nz = nz; gq.ty = ty; gq.ntiles = ny / ty; gq.N = N;
     ARG_CHECK(geom_supported(gq), "n[2] must be <= 116");
+    const int blk = ((ty * nz + 63) / 64) * 64;
+    ARG_CHECK(p->n_proj < 0 ||
+              cocg_shmem_bytes(gq, blk, p->precision == RPA_FP32_REFINE, p->n_proj) <= 160 * 1024,
+              "projector coefficients and stencil planes exceed the 160 KiB of LDS");
+  }
+  NlHost nlh;
+  {
+    double dV = 1.0;
+    for (int d = 0; d < 3; ++d) dV *= p->L[d] / p->n[d];
+    const std::string nerr = nl_build(p, N, dV, nlh);
+    ARG_CHECK(nerr.empty(), nerr);
   }
 
   rpa_ctx* h = new rpa_ctx();
@@ -595,6 +685,28 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
     if (!alloc((void**)&h->Vax[d], (size_t)h->n[d] * h->n[d] * sizeof(double))) return fail(RPA_E_OOM);
   h->eps_h.assign(p->eps, p->eps + h->nocc);
 
+  // nonlocal projector layouts
+  struct Upload { void* dst; const void* src; size_t bytes; };
+  std::vector<Upload> nl_up;
+  if (p->n_proj > 0) {
+    auto up = [&](auto& dst, const auto& v) -> bool {
+      using E = typename std::decay_t<decltype(v)>::value_type;
+      void* d = nullptr;
+      if (!alloc(&d, std::max<size_t>(1, v.size()) * sizeof(E))) return false;
+      h->nl_mem.push_back(d);
+      dst = reinterpret_cast<std::decay_t<decltype(dst)>>(d);
+      nl_up.push_back({d, v.data(), v.size() * sizeof(E)});
+      return true;
+    };
+    h->nl.n_proj = p->n_proj;
+    h->nl.n_groups = (int)nlh.ginfo.size();
+    if (!up(h->nl.ginfo, nlh.ginfo) || !up(h->nl.gvoff, nlh.gvoff) || !up(h->nl.bidx, nlh.bidx) ||
+        !up(h->nl.bv32, nlh.bv32) || !up(h->nl.bv64, nlh.bv64) || !up(h->nl.gdv, nlh.gdv) ||
+        !up(h->nl.pm_ptr, nlh.pm_ptr) || !up(h->nl.pm_proj, nlh.pm_proj) ||
+        !up(h->nl.pm_v32, nlh.pm_v32) || !up(h->nl.pm_v64, nlh.pm_v64))
+      return fail(RPA_E_OOM);
+  }
+
   std::vector<double> V[3], lam[3];
   for (int d = 0; d < 3; ++d) axis_basis(h->n[d], h->h[d], w, kRadius, V[d], lam[d]);
   std::vector<double> sh((size_t)N), sf((size_t)N);
@@ -614,6 +726,9 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   if (e == hipSuccess) e = hipMemcpyAsync(h->s_full, sf.data(), N * sizeof(double), hipMemcpyHostToDevice, s);
   for (int d = 0; d < 3 && e == hipSuccess; ++d)
     e = hipMemcpyAsync(h->Vax[d], V[d].data(), V[d].size() * sizeof(double), hipMemcpyHostToDevice, s);
+  for (size_t k = 0; k < nl_up.size() && e == hipSuccess; ++k)
+    if (nl_up[k].bytes)
+      e = hipMemcpyAsync(nl_up[k].dst, nl_up[k].src, nl_up[k].bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_d2f(h->v64, h->v32, N, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -631,6 +746,8 @@ rpa_status rpa_destroy(rpa_handle h) {
   (void)hipDeviceSynchronize();
   auto fr = [](void* p) { if (p) (void)hipFree(p); };
   fr(h->v64); fr(h->v32); fr(h->psi64); fr(h->eps_d); fr(h->s_half); fr(h->s_full);
+  for (void* m : h->nl_mem) fr(m);
+  fr(h->nlcoef.p);
   for (int d = 0; d < 3; ++d) fr(h->Vax[d]);
   DevBuf* bufs[] = {&h->x64, &h->slots, &h->u64, &h->racc, &h->vtmp, &h->tmpA, &h->Q, &h->alpha,
                     &h->beta, &h->mlen, &h->active, &h->order, &h->iters, &h->cycles, &h->status,
@@ -656,7 +773,8 @@ rpa_status rpa_release_workspace(rpa_handle h) {
   ++h->alloc_epoch;
   DevBuf* bufs[] = {&h->x64, &h->slots, &h->u64, &h->racc, &h->vtmp, &h->tmpA, &h->Q, &h->alpha,
                     &h->beta, &h->mlen, &h->active, &h->order, &h->iters, &h->cycles, &h->status,
-                    &h->counter, &h->gpart, &h->G, &h->dhat, &h->partials, &h->shifts, &h->dres};
+                    &h->counter, &h->gpart, &h->G, &h->dhat, &h->partials, &h->shifts, &h->dres,
+                    &h->nlcoef};
   for (DevBuf* b : bufs) {
     if (b->p) {
       (void)hipFree(b->p);
@@ -686,6 +804,10 @@ rpa_status rpa_hamiltonian_apply(rpa_handle h, int32_t nvec, const double* shift
                           P<double>(h->shifts) + nvec, x, y, precision == RPA_FP32_REFINE,
                           h->block, s));
   HIPCHK(h, hipEventRecord(h->ev1, s));
+  if (h->nl.n_proj > 0) {
+    ENSURE(h, h->nlcoef, (size_t)nvec * h->nl.n_proj * sizeof(double2));
+    HIPCHK(h, launch_nl_apply(h->nl, h->N, nvec, x, y, h->nlcoef.p, precision == RPA_FP32_REFINE, s));
+  }
   HIPCHK(h, hipStreamSynchronize(s));
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->last_ms = ms;

@@ -11,6 +11,8 @@ constexpr int kRadius = 6;               // 12th-order central differences
 constexpr int kMaxLanczos = 64;          // largest supported n_lanczos
 constexpr int kMaxLanczosPublic = kMaxLanczos;
 constexpr int kMaxBlock = 768;           // largest stencil/COCG workgroup
+constexpr int kMaxProj = 4096;           // projectors (their coefficients live in LDS)
+constexpr int kMaxGroup = 4;             // projectors sharing one support per group
 
 // (H - eps_n - i omega) p = (c0 + V - eps_n) p - i omega p
 //                          + sum_d s_d sum_k w[k] (p_{+k e_d} + p_{-k e_d}),
@@ -27,6 +29,27 @@ struct Geom {
   int ty;          // rows per tile
   int ntiles;      // ny / ty
   long long N;     // nx*ny*nz
+};
+
+// Separable nonlocal projectors V_nl = h^3 sum_p gamma_p chi_p chi_p^T
+// (Background section) in two layouts: by support ("groups" of up to
+// kMaxGroup consecutive projectors with identical support, e.g. the angular
+// channels of one atom) for the projections c_p = chi_p^T x, and by grid
+// point for the sums (V_nl x)_i = sum_p (gamma_p h^3 c_p) chi_p(i).
+// n_proj == 0: no nonlocal term (all pointers null).
+struct NlArgs {
+  int n_proj;
+  int n_groups;
+  const int4* ginfo;       // [n_groups] {first support entry, end, first projector, count}
+  const int* gvoff;        // [n_groups] offset of the group's values, stored [count][S]
+  const int* bidx;         // support grid indices of all groups
+  const float* bv32;       // group values
+  const double* bv64;
+  const double* gdv;       // [n_proj] gamma_p * h^3
+  const int* pm_ptr;       // [N + 1] entries of point i: pm_ptr[i] .. pm_ptr[i+1]-1
+  const int* pm_proj;      // projector of each entry
+  const float* pm_v32;     // chi_p(i) of each entry
+  const double* pm_v64;
 };
 
 // Arguments of the persistent COCG launch.
@@ -56,13 +79,14 @@ struct CocgArgs {
   int maxit;
   double inner_tol;            // FP32 inner relative reduction
   int max_cycles;
+  NlArgs nl;
 };
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_cocg(const CocgArgs& a, bool fp32_refine, int grid, int block, size_t shmem,
                        hipStream_t s);
-size_t cocg_shmem_bytes(const Geom& g, int block, bool fp32_refine);
-int cocg_blocks_per_cu(const Geom& g, int block, bool fp32_refine);
+size_t cocg_shmem_bytes(const Geom& g, int block, bool fp32_refine, int n_proj);
+int cocg_blocks_per_cu(const Geom& g, int block, bool fp32_refine, int n_proj);
 bool geom_supported(const Geom& g);   // nz + 12 <= 128 (padded LDS rows)
 long long cocg_slot_bytes(const Geom& g, bool fp32_refine);
 
@@ -70,6 +94,10 @@ hipError_t launch_happly(const Geom& g, const StencilCoef<double>& c64, const St
                          const double* v64, const float* v32, int nvec, const double* shift_re,
                          const double* shift_im, const void* x, void* y, bool fp32,
                          int block, hipStream_t s);
+// y[v] += V_nl x[v] for nvec vectors of N points (complex, FP32 or FP64);
+// coef: workspace of nvec * n_proj complex values of that precision.
+hipError_t launch_nl_apply(const NlArgs& nl, long long N, int nvec, const void* x, void* y,
+                           void* coef, bool fp32, hipStream_t s);
 
 hipError_t launch_fill_d(double* p, double v, long long n, hipStream_t s);
 hipError_t launch_fill_i(int* p, int v, long long n, hipStream_t s);

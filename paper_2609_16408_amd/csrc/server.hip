@@ -31,6 +31,8 @@ double now_s() {
 struct CellDef {
   rpa_setup_params prm;           // pointers below refer to the server's copies
   std::vector<double> eps;
+  std::vector<int64_t> proj_ptr, proj_idx;   // host copies of the projectors
+  std::vector<double> proj_val, proj_gamma;
   double* v = nullptr;            // device copies (real executor only)
   double* psi = nullptr;
   long long N = 0;
@@ -169,7 +171,7 @@ rpa_status rpa_server_create(const rpa_server_params* p, rpa_server* out) {
 
 rpa_status rpa_server_add_cell(rpa_server S, const rpa_setup_params* p, int32_t* cell_id) {
   if (!S || !p || !cell_id) return RPA_E_ARG;
-  if (p->n_proj != 0) return RPA_E_ARG;
+  if (p->n_proj < 0 || p->n_proj > rpa::kMaxProj) return RPA_E_ARG;
   auto c = std::make_unique<CellDef>();
   c->prm = *p;
   c->N = (long long)p->n[0] * p->n[1] * p->n[2];
@@ -177,6 +179,20 @@ rpa_status rpa_server_add_cell(rpa_server S, const rpa_setup_params* p, int32_t*
   if (c->N <= 0 || c->nocc < 1 || !p->eps) return RPA_E_ARG;
   c->eps.assign(p->eps, p->eps + p->n_occ);
   c->prm.eps = c->eps.data();
+  if (p->n_proj > 0) {
+    // the workers' rpa_setup validates the contents; only the extents here
+    if (!p->proj_ptr || !p->proj_idx || !p->proj_val || !p->proj_gamma) return RPA_E_ARG;
+    const int64_t nnz = p->proj_ptr[p->n_proj];
+    if (p->proj_ptr[0] != 0 || nnz < 0) return RPA_E_ARG;
+    c->proj_ptr.assign(p->proj_ptr, p->proj_ptr + p->n_proj + 1);
+    c->proj_idx.assign(p->proj_idx, p->proj_idx + nnz);
+    c->proj_val.assign(p->proj_val, p->proj_val + nnz);
+    c->proj_gamma.assign(p->proj_gamma, p->proj_gamma + p->n_proj);
+    c->prm.proj_ptr = c->proj_ptr.data();
+    c->prm.proj_idx = c->proj_idx.data();
+    c->prm.proj_val = c->proj_val.data();
+    c->prm.proj_gamma = c->proj_gamma.data();
+  }
   const uint64_t bytes = (uint64_t)c->N * 8 * (1 + (uint64_t)c->nocc);
   if (S->prm.fake_executor_us == 0) {
     if (!p->v_loc || !p->psi) return RPA_E_ARG;

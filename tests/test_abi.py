@@ -53,3 +53,33 @@ def test_null_handle_is_rejected():
     L = P.lib()
     st = L.interpolate(None, 1, 2, 1, None, None, None)
     assert st == P.RPA_E_ARG
+
+
+@pytest.mark.parametrize("case,msg", [
+    ("idx", b"proj_idx out of range"), ("ptr", b"non-decreasing"), ("count", b"n_proj"),
+    ("null", b"required"), ("gamma", b"proj_gamma must be finite")])
+def test_setup_rejects_bad_projectors_without_a_gpu(case, msg):
+    """Projector layouts are validated on the host before any device call."""
+    L = P.lib()
+    N = 12 ** 3
+    eps = np.array([-0.5, -0.4])
+    dummy = np.zeros(1)
+    prm = P._setup_params((12, 12, 12), (10.0, 10.0, 10.0), dummy.ctypes.data,
+                          dummy.ctypes.data, eps, "fp64", 1e-8, 100)
+    proj = {"ptr": np.array([0, 3, 6]), "idx": np.array([0, 1, 2, 5, 6, N - 1]),
+            "val": np.ones(6), "gamma": np.array([1.0, 2.0])}
+    if case == "idx":
+        proj["idx"][4] = N
+    if case == "ptr":
+        proj["ptr"] = np.array([0, 4, 3])
+    if case == "gamma":
+        proj["gamma"][1] = np.nan
+    keep = P._set_proj(prm, proj)
+    if case == "count":
+        prm.n_proj = 5000
+    if case == "null":
+        prm.proj_val = None
+    h = ctypes.c_void_p()
+    assert L.rpa_setup(ctypes.byref(prm), None, ctypes.byref(h)) == P.RPA_E_ARG
+    assert msg in L.rpa_last_error(None), L.rpa_last_error(None)
+    del keep

@@ -143,6 +143,105 @@ def test_chi0_apply_invariants(P, tiny):
     h.close()
 
 
+# --- nonlocal projectors --------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def tiny_nl():
+    return sc.preset("tiny", with_projectors=True, proj_seed=201)
+
+
+@pytest.fixture(scope="module")
+def tiny_nl_ops(tiny_nl):
+    c = tiny_nl
+    return O.Hamiltonian(c.n, c.L, c.v_loc, proj=c.proj), O.Coulomb(c.n, c.L)
+
+
+@pytest.fixture(scope="module")
+def tiled_nl():
+    """1x2x2 cell on 12 x 24 x 48 with projectors: two y tiles of 12 rows."""
+    c = sc.make_cell("tiled_nl", cells=(1, 2, 2), n=(12, 24, 48), n_occ=16, seed=31,
+                     with_projectors=True, proj_seed=231)
+    sc.ks_orbitals(c)
+    return c
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_hamiltonian_apply_with_projectors_matches_oracle(P, tiny_nl, tiled_nl, precision):
+    for c in (tiny_nl, tiled_nl):
+        h = _handle(P, c)
+        x = _cplx((3, c.N_d), 41)
+        shifts = np.array([-0.4 + 0.02j, 0.3 + 1.5j, 0.0 + 49.0j])
+        y = h.hamiltonian_apply(shifts, torch.from_numpy(x), precision=precision).cpu().numpy()
+        ham = O.Hamiltonian(c.n, c.L, c.v_loc, proj=c.proj)
+        for i in range(3):
+            ref = ham.apply(x[i]) - shifts[i] * x[i]
+            err = np.abs(y[i] - ref).max() / np.abs(ref).max()
+            assert err < (1e-13 if precision == "fp64" else 2e-6), (c.name, i, err)
+        h.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_chi0_apply_with_projectors_matches_oracle(P, tiny_nl, tiny_nl_ops, tiled_nl, precision):
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    for c, omega in ((tiny_nl, 0.69), (tiny_nl, 0.0203), (tiled_nl, 0.31)):
+        ham = tiny_nl_ops[0] if c is tiny_nl else O.Hamiltonian(c.n, c.L, c.v_loc, proj=c.proj)
+        h = _handle(P, c, precision=precision, stern_tol=tol)
+        x = np.random.default_rng(43).standard_normal((2, c.N_d))
+        y, st = h.chi0_apply(omega, torch.from_numpy(x))
+        y = y.cpu().numpy()
+        assert st["n_noconv"] == 0
+        for i in range(2):
+            # direct sparse solves on the small cell, oracle COCG on the larger one
+            ref = O.chi0_apply(ham, c.psi, c.eps, x[i], omega, exact=c is tiny_nl, tol=1e-11)
+            err = np.abs(y[i] - ref).max() / np.abs(ref).max()
+            assert err <= 20 * tol, (c.name, omega, i, err)
+        h.close()
+
+
+def test_lanczos_with_projectors_matches_oracle(P, tiny_nl, tiny_nl_ops):
+    ham, coul = tiny_nl_ops
+    om = np.array([0.31, 3.2])
+    pts = np.array([0, 777, 1500, 1727])
+    h = _handle(P, tiny_nl, stern_tol=1e-10, batch=3)
+    d, st = h.lanczos_energy_density(om, pts, 6)
+    ref = O.energy_density(ham, coul, tiny_nl.psi, tiny_nl.eps, om, pts, 6, tol=1e-10)
+    assert np.abs(d.cpu().numpy() - ref).max() <= 1e-8
+    h.close()
+
+
+@pytest.fixture(scope="module")
+def si216_shape():
+    """The 3x3x3 cell (72^3 grid, 216 atoms, 864 projectors) without orbitals:
+    one normalised random orbital below the spectrum, so single Sternheimer
+    systems at the full grid size stay within reach of the oracle."""
+    c = sc.preset("si216", orbitals=False)
+    rng = np.random.default_rng(216)
+    psi = rng.standard_normal((1, c.N_d))
+    psi /= np.sqrt(c.dV * (psi * psi).sum())
+    eps = np.array([float(c.v_loc.min()) - 1.0])
+    ham = O.Hamiltonian(c.n, c.L, c.v_loc, proj=c.proj)
+    return c, psi, eps, ham
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refine"])
+def test_si216_shape_operator_and_chi0_match_oracle(P, si216_shape, precision):
+    c, psi, eps, ham = si216_shape
+    h = P.Handle(c.n, c.L, c.v_loc, psi, eps, precision=precision,
+                 stern_tol=1e-10 if precision == "fp64" else 1e-8, proj=c.proj)
+    x = _cplx((1, c.N_d), 44)
+    y = h.hamiltonian_apply([0.3 + 0.7j], torch.from_numpy(x), precision=precision)
+    ref = ham.apply(x[0]) - (0.3 + 0.7j) * x[0]
+    err = np.abs(y.cpu().numpy()[0] - ref).max() / np.abs(ref).max()
+    assert err < (1e-13 if precision == "fp64" else 2e-6), err
+    u = np.random.default_rng(45).standard_normal((1, c.N_d))
+    r, st = h.chi0_apply(0.69, torch.from_numpy(u))
+    assert st["n_noconv"] == 0
+    ref = O.chi0_apply(ham, psi, eps, u[0], 0.69, tol=1e-11)
+    err = np.abs(r.cpu().numpy()[0] - ref).max() / np.abs(ref).max()
+    assert err <= (1e-8 if precision == "fp64" else 2e-7), err
+    h.close()
+
+
 # --- Lanczos quadrature --------------------------------------------------------------
 
 def test_lanczos_energy_density_tiny_matches_oracle(P, tiny, tiny_ops):
