@@ -23,7 +23,7 @@ if ROOT not in sys.path:
 
 METRIC = "RPA energy-density points/s, Si64 FP32+refine vs FP64; stencil GB/s; p99 latency"
 HBM_PEAK_GBPS = 8000.0
-COCG_SRC = os.path.join(ROOT, "paper_2609_16408_amd", "csrc", "cocg.hip")
+COCG_SRC = [os.path.join(ROOT, "paper_2609_16408_amd", "csrc", f) for f in ("cocg_impl.h", "cocg.hip")]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_cocg_si64_hbm_traffic.md")
 CALIB_BYTES = 1 << 30
 
@@ -60,7 +60,10 @@ def cocg_algorithmic_bytes(st: dict, N: int, precision: str) -> float:
 
 def source_sha():
     import hashlib
-    return hashlib.sha256(open(COCG_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in COCG_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def pmc_traffic(workload):

@@ -184,6 +184,28 @@ rpa_status rpa_coulomb_apply(rpa_handle h, int32_t power, int32_t nvec, const do
 rpa_status rpa_last_cocg_timing(rpa_handle h, double* ms, int32_t* launches, int32_t* grid,
                                 int32_t* block, int32_t* tile_y);
 
+/* Launch-shape tuning (the handle's tile rows, workgroups per CU and start
+ * vectors per launch).  Each candidate shape -- the whole (y, z) plane if it
+ * fits a workgroup, else the four tallest row counts that divide n[1], with
+ * one or two workgroups per CU where occupancy allows -- runs a fixed-work
+ * probe: one-hot start vectors through nu^1/2 at omega = 0.69, every
+ * Sternheimer system for exactly probe_iters COCG iterations (0: 16); the
+ * fastest in system-iterations per second is kept.  batch becomes the most
+ * start vectors (at most 64) whose workspaces for n_lanczos steps fit the
+ * hbm_budget, or 80% of the free device memory when there is none.  Later
+ * results change by rounding only: each system's reductions follow the
+ * workgroup shape, which the tile rows set (workgroups per CU and batch do
+ * not change any result bit).  Invalidates captured graphs.  out: host. */
+typedef struct {
+  int32_t tile_y;
+  int32_t slots_per_cu;
+  int32_t batch;
+  int32_t n_tried;             /* shapes timed */
+  double system_iters_per_s;   /* probe rate of the chosen shape */
+} rpa_tune_result;
+rpa_status rpa_autotune(rpa_handle h, int32_t n_lanczos, int32_t probe_iters,
+                        rpa_tune_result* out, void* stream);
+
 /* Release every workspace of the handle (resident problem data stays). */
 rpa_status rpa_release_workspace(rpa_handle h);
 

@@ -60,6 +60,15 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("tile_y", ctypes.c_int32), ("slots_per_cu", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("n_tried", ctypes.c_int32),
+                ("system_iters_per_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class ServerParams(ctypes.Structure):
     _fields_ = [("n_workers", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64),
                 ("fake_executor_us", ctypes.c_int32)]
@@ -92,6 +101,7 @@ _SIGS = {
     "rpa_coulomb_apply": [_VP, _I32, _I32, _VP, _VP, _VP],
     "rpa_last_cocg_timing": [_VP, _VP, _VP, _VP, _VP, _VP],
     "rpa_release_workspace": [_VP],
+    "rpa_autotune": [_VP, _I32, _I32, ctypes.POINTER(TuneResult), _VP],
     "rpa_server_create": [_VP, _VP],
     "rpa_server_add_cell": [_VP, ctypes.POINTER(SetupParams), _VP],
     "rpa_server_submit": [_VP, _I32, _D, _I32, _VP, _I32, _VP, _VP],
@@ -196,6 +206,13 @@ class Handle:
         del keep
         self._h = h
         self.precision = precision
+
+    def autotune(self, n_lanczos=8, probe_iters=0, stream=None):
+        """Time the candidate launch shapes and keep the fastest (rpa_autotune)."""
+        res = TuneResult()
+        _check(lib().rpa_autotune(self._h, int(n_lanczos), int(probe_iters), ctypes.byref(res),
+                                  _stream(stream)), "rpa_autotune")
+        return res.as_dict()
 
     def release_workspace(self):
         """Free the workspaces (resident cell data stays); captured graphs are dropped."""

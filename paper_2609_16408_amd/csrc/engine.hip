@@ -1085,6 +1085,120 @@ rpa_status correlation_energy(rpa_handle h, int32_t n_omega, const double* omega
   return warn;
 }
 
+rpa_status rpa_autotune(rpa_handle h, int32_t n_lanczos, int32_t probe_iters,
+                        rpa_tune_result* out, void* stream) {
+  rpa_status u = usable(h);
+  if (u != RPA_OK) return u;
+  ARG_CHECK(out, "null output");
+  ARG_CHECK(n_lanczos >= 1 && n_lanczos <= kMaxLanczos, "n_lanczos must be in [1, 64]");
+  ARG_CHECK(probe_iters >= 0 && probe_iters <= 1000, "probe_iters must be in [0, 1000]");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const long long N = h->N;
+  const int nocc = h->nocc;
+  const int ny = h->geom.ny, nz = h->geom.nz;
+  const bool refine = h->precision == RPA_FP32_REFINE;
+  const int K = probe_iters > 0 ? probe_iters : 16;
+  memset(out, 0, sizeof(*out));
+
+  // candidate tiles: the whole plane if it fits, then the four tallest
+  // divisors of ny with ty >= 6 (shorter tiles re-read more halo rows)
+  std::vector<int> tys;
+  for (int t = ny; t >= kRadius && tys.size() < 4; --t) {
+    if (ny % t || ((t * nz + 63) / 64) * 64 > kMaxBlock) continue;
+    Geom gq = h->geom;
+    gq.ty = t;
+    gq.ntiles = ny / t;
+    const int blk = ((t * nz + 63) / 64) * 64;
+    if (cocg_shmem_bytes(gq, blk, refine, h->nl.n_proj) > 160 * 1024) continue;
+    tys.push_back(t);
+  }
+  if (tys.empty()) return set_err(RPA_E_STATE, "no tile shape fits");
+
+  // fixed-work probe: one-hot start vectors through nu^1/2, omega = 0.69,
+  // exactly K COCG iterations per system (tolerance out of reach)
+  const Geom g0 = h->geom;
+  const int blk0 = h->block, slots0 = h->slots_per_cu;
+  const double tol0 = h->tol;
+  const int maxit0 = h->maxit;
+  auto restore = [&]() {
+    h->geom = g0; h->block = blk0; h->slots_per_cu = slots0; h->tol = tol0; h->maxit = maxit0;
+  };
+  const int Bp = (int)std::min<long long>(64, std::max<long long>(1, (2LL * h->num_cu * 2 + nocc - 1) / nocc));
+  rpa_status r = begin_stats(h, s);
+  if (r != RPA_OK) return r;
+  ENSURE(h, h->Q, (size_t)Bp * N * sizeof(double));
+  ENSURE(h, h->u64, (size_t)Bp * N * sizeof(double));
+  ENSURE(h, h->omega_b, (size_t)Bp * sizeof(double));
+  ENSURE(h, h->idx_b, (size_t)Bp * sizeof(long long));
+  std::vector<double> om(Bp, 0.69);
+  std::vector<long long> idx(Bp);
+  for (int b = 0; b < Bp; ++b) idx[b] = (long long)((N - 1) * (double)b / std::max(1, Bp - 1));
+  HIPCHK(h, hipMemcpyAsync(h->omega_b.p, om.data(), Bp * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->idx_b.p, idx.data(), Bp * sizeof(long long), hipMemcpyHostToDevice, s));
+  HIPCHK(h, launch_fill_d(P<double>(h->Q), 0.0, (long long)Bp * N, s));
+  HIPCHK(h, launch_set_onehot(P<double>(h->Q), N, P<long long>(h->idx_b), Bp, s));
+  r = coulomb(h, 1, Bp, P<double>(h->Q), P<double>(h->u64), s);
+  if (r != RPA_OK) return r;
+  HIPCHK(h, hipStreamSynchronize(s));
+
+  double best = -1.0;
+  int best_ty = g0.ty, best_slots = 1;
+  h->tol = 1e-300;
+  h->maxit = K;
+  for (int t : tys) {
+    h->geom.ty = t;
+    h->geom.ntiles = ny / t;
+    h->block = ((t * nz + 63) / 64) * 64;
+    const int occ = cocg_blocks_per_cu(h->geom, h->block, refine, h->nl.n_proj);
+    for (int slots = 1; slots <= std::min(2, occ); ++slots) {
+      h->slots_per_cu = slots;
+      float ms = 0.f;
+      for (int rep = 0; rep < 3; ++rep) {   // first run warms up
+        if (rep == 1) HIPCHK(h, hipEventRecord(h->ev0, s));
+        r = sternheimer_batch(h, Bp, om, nullptr, s, true, false);
+        if (r != RPA_OK) { restore(); return r; }
+      }
+      HIPCHK(h, hipEventRecord(h->ev1, s));
+      HIPCHK(h, hipStreamSynchronize(s));
+      if (hipEventElapsedTime(&ms, h->ev0, h->ev1) != hipSuccess) { restore(); return set_err(RPA_E_HIP, "timing failed"); }
+      const double rate = 2.0 * Bp * nocc * K / (ms * 1e-3);   // system-iterations per s
+      ++out->n_tried;
+      if (rate > best) { best = rate; best_ty = t; best_slots = slots; }
+    }
+  }
+  restore();
+  h->geom.ty = best_ty;
+  h->geom.ntiles = ny / best_ty;
+  h->block = ((best_ty * nz + 63) / 64) * 64;
+  h->slots_per_cu = best_slots;
+  drop_graphs(h);
+  h->warm_B = 0;
+  h->warm_m = 0;
+  ++h->alloc_epoch;
+
+  // start vectors per launch: as many as fit (at most 64) in the budget, or
+  // in 80% of the free device memory, next to what is allocated already
+  const size_t per_vec = (size_t)nocc * N * sizeof(double2) + (size_t)n_lanczos * N * sizeof(double) +
+                         6 * (size_t)N * sizeof(double);
+  size_t avail = 0;
+  if (h->budget) {
+    avail = h->budget > h->allocated ? h->budget - h->allocated : 0;
+  } else {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) { (void)hipGetLastError(); fr = 0; }
+    avail = (size_t)(0.8 * (double)fr);
+  }
+  const int grid_slots = best_slots * h->num_cu;
+  const size_t slots_bytes = (size_t)grid_slots * cocg_slot_bytes(h->geom, refine);
+  avail = avail > slots_bytes ? avail - slots_bytes : 0;
+  h->batch = (int)std::max<size_t>(1, std::min<size_t>(64, avail / per_vec));
+  out->tile_y = best_ty;
+  out->slots_per_cu = best_slots;
+  out->batch = h->batch;
+  out->system_iters_per_s = best;
+  return RPA_OK;
+}
+
 rpa_status rpa_last_cocg_timing(rpa_handle h, double* ms, int32_t* launches, int32_t* grid,
                                 int32_t* block, int32_t* tile_y) {
   if (!h) return set_err(RPA_E_ARG, "null handle");

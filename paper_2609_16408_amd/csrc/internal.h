@@ -85,6 +85,10 @@ struct CocgArgs {
 // Launchers (return hipError_t of the launch).
 hipError_t launch_cocg(const CocgArgs& a, bool fp32_refine, int grid, int block, size_t shmem,
                        hipStream_t s);
+// the kernels with the nonlocal term (separate translation unit)
+hipError_t launch_cocg_nl(const CocgArgs& a, bool fp32_refine, int grid, int block, size_t shmem,
+                          hipStream_t s);
+const void* cocg_nl_fn(bool fp32_refine, int tile_mode, int pitch);
 size_t cocg_shmem_bytes(const Geom& g, int block, bool fp32_refine, int n_proj);
 int cocg_blocks_per_cu(const Geom& g, int block, bool fp32_refine, int n_proj);
 bool geom_supported(const Geom& g);   // nz + 12 <= 128 (padded LDS rows)

@@ -242,6 +242,46 @@ def test_si216_shape_operator_and_chi0_match_oracle(P, si216_shape, precision):
     h.close()
 
 
+# --- launch-shape tuning ------------------------------------------------------------
+
+def test_autotune_picks_a_valid_shape_and_keeps_results(P, long_cell, tmp_path):
+    import paper_2609_16408_amd.tuning as T
+    c = long_cell
+    ham = O.Hamiltonian(c.n, c.L, c.v_loc)
+    x = np.random.default_rng(51).standard_normal((2, c.N_d))
+    h = _handle(P, c, precision="fp32_refine", stern_tol=1e-8)
+    y0, _ = h.chi0_apply(0.31, torch.from_numpy(x))
+    shape = h.autotune(n_lanczos=8)
+    assert c.n[1] % shape["tile_y"] == 0 and shape["tile_y"] * c.n[2] <= 768
+    assert shape["slots_per_cu"] in (1, 2) and 1 <= shape["batch"] <= 64 and shape["n_tried"] >= 1
+    assert h.last_cocg_timing()["tile_y"] == shape["tile_y"]
+    y1, st = h.chi0_apply(0.31, torch.from_numpy(x))
+    assert st["n_noconv"] == 0
+    for i in range(2):
+        ref = O.chi0_apply(ham, c.psi, c.eps, x[i], 0.31, tol=1e-11)
+        assert np.abs(y1[i].cpu().numpy() - ref).max() <= 2e-7 * np.abs(ref).max()
+    h.close()
+    # same tile rows: workgroups per CU and batch change no bit
+    h2 = _handle(P, c, precision="fp32_refine", stern_tol=1e-8, tile_y=shape["tile_y"],
+                 slots_per_cu=shape["slots_per_cu"], batch=shape["batch"])
+    h3 = _handle(P, c, precision="fp32_refine", stern_tol=1e-8, tile_y=shape["tile_y"],
+                 slots_per_cu=1, batch=1)
+    assert torch.equal(h2.chi0_apply(0.31, torch.from_numpy(x))[0],
+                       h3.chi0_apply(0.31, torch.from_numpy(x))[0])
+    h2.close()
+    h3.close()
+    # the cache: a miss tunes and stores, a hit reuses the stored shape
+    path = str(tmp_path / "tune.json")
+    ha, sa, hit_a = T.tuned_handle_for_cell(c, n_lanczos=8, cache_path=path,
+                                            precision="fp32_refine", stern_tol=1e-8)
+    hb, sb, hit_b = T.tuned_handle_for_cell(c, n_lanczos=8, cache_path=path,
+                                            precision="fp32_refine", stern_tol=1e-8)
+    assert not hit_a and hit_b and sa == sb
+    assert hb.last_cocg_timing()["tile_y"] == sa["tile_y"]
+    ha.close()
+    hb.close()
+
+
 # --- Lanczos quadrature --------------------------------------------------------------
 
 def test_lanczos_energy_density_tiny_matches_oracle(P, tiny, tiny_ops):
