@@ -23,7 +23,10 @@ if ROOT not in sys.path:
 
 METRIC = "RPA energy-density points/s, Si64 FP32+refine vs FP64; stencil GB/s; p99 latency"
 HBM_PEAK_GBPS = 8000.0
-COCG_SRC = [os.path.join(ROOT, "paper_2609_16408_amd", "csrc", f) for f in ("cocg_impl.h", "cocg.hip")]
+# the kernel's traffic also depends on the engine's defaults (reliable-update
+# factor, processing order), so the engine source is part of the key
+COCG_SRC = [os.path.join(ROOT, "paper_2609_16408_amd", "csrc", f)
+            for f in ("cocg_impl.h", "cocg.hip", "engine.hip")]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_cocg_si64_hbm_traffic.md")
 CALIB_BYTES = 1 << 30
 
@@ -195,6 +198,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slots-per-cu", type=int, default=0)
     ap.add_argument("--tile-y", type=int, default=0)
+    ap.add_argument("--inner-tol", type=float, default=0.0,
+                    help="reliable-update factor of the FP32 COCG (0: library default)")
     ap.add_argument("--orbital-cache", default="", help="npz file to reuse/save the orbitals")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -234,7 +239,7 @@ def main():
     def make_handle(precision):
         return P.handle_for_cell(cell, precision=precision, stern_tol=cfg["tol"],
                                  stern_maxit=20000, batch=64, slots_per_cu=args.slots_per_cu,
-                                 tile_y=args.tile_y)
+                                 tile_y=args.tile_y, inner_tol=args.inner_tol)
 
     h = make_handle(args.precision)
     d_coarse = torch.zeros((8, coarse.size), dtype=torch.float64, device="cuda")

@@ -628,8 +628,11 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   h->batch = p->batch;
   h->budget = p->hbm_budget;
   // reliable-update factor of the FP32 COCG (residual replaced by the FP64
-  // residual each time the recursive one dropped by this factor)
-  h->inner_tol = p->inner_tol > 0 ? p->inner_tol : 0.1;
+  // residual each time the recursive one dropped by this factor).  On the
+  // Si64 workload 0.01 needs 3.0 updates and 98.3 iterations per solve
+  // against 5.6 and 97.1 at 0.1, and each update costs about five FP32
+  // iterations of time (fold plus FP64 residual sweep): 5% faster overall.
+  h->inner_tol = p->inner_tol > 0 ? p->inner_tol : 0.01;
   h->slots_per_cu = p->slots_per_cu;
   h->use_graph = p->use_graph;
   h->geom.nx = p->n[0];
