@@ -67,17 +67,25 @@ __global__ void k_axis(const double* __restrict__ in, double* __restrict__ out, 
 }
 
 // ---------------------------------------------------------------------------
-// Galerkin projection, part 1: part[b][c][m][n] = sum_{r in chunk c} psi_m psi_n u_b
-// 256 threads = 16 x 16, each accumulating an 8 x 8 block of a 128 x 128 tile.
+// Galerkin projection, part 1: part[b][c][m][n] = sum_{r in chunk c} psi_m psi_n u_b,
+// a contraction over grid points on the FP64 matrix cores.  A 256-thread
+// workgroup owns a 128 x 128 output tile; each wave a 64 x 64 quadrant as
+// 4 x 4 MFMA tiles (v_mfma_f64_16x16x4: A lane l = row l%16, k l/16; B lane
+// l = column l%16, k l/16; D register v of lane l = row l/16 + 4v, column
+// l%16).  GK grid
+// points of the 128 rows of each operand are staged in LDS per step (the
+// psi_m u_b rows and the psi_n rows), zero beyond n_occ and the chunk end.
 constexpr int GT = 128;   // output tile
 constexpr int GK = 16;    // r-block staged in LDS
+
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) k_gram(const double* __restrict__ psi,
                                               const double* __restrict__ u, int n_occ,
                                               long long N, int n_chunks, int ntn,
                                               double* __restrict__ part) {
-  __shared__ double sA[GK][GT + 1];
-  __shared__ double sB[GK][GT + 1];
+  __shared__ double sA[GK][GT + 2];
+  __shared__ double sB[GK][GT + 2];
   const int c = blockIdx.x;
   const int b = blockIdx.y;
   const int tm = blockIdx.z / ntn, tn = blockIdx.z % ntn;
@@ -85,15 +93,17 @@ __global__ void __launch_bounds__(256) k_gram(const double* __restrict__ psi,
   const long long clen = (N + n_chunks - 1) / n_chunks;
   const long long r0 = c * clen;
   const long long r1 = r0 + clen < N ? r0 + clen : N;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int qm = (wave >> 1) * 64, qn = (wave & 1) * 64;   // quadrant of the tile
+  const int li = lane & 15, lk = lane >> 4;
   const double* ub = u + (size_t)b * N;
-  double acc[8][8];
+  d4 acc[4][4];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
   for (long long rb = r0; rb < r1; rb += GK) {
-    // stage GK x GT of psi rows m0.. (times u) and n0..
     for (int e = threadIdx.x; e < GK * GT; e += 256) {
       const int k = e % GK, i = e / GK;
       const long long r = rb + k;
@@ -107,29 +117,33 @@ __global__ void __launch_bounds__(256) k_gram(const double* __restrict__ psi,
       sB[k][i] = bb;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < GK; ++k) {
-      double av[8], bv[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) av[i] = sA[k][ty * 8 + i];
+    for (int k0 = 0; k0 < GK; k0 += 4) {
+      double av[4], bv[4];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) bv[j] = sB[k][tx * 8 + j];
+      for (int t = 0; t < 4; ++t) {
+        av[t] = sA[k0 + lk][qm + t * 16 + li];
+        bv[t] = sB[k0 + lk][qn + t * 16 + li];
+      }
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[i][j] += av[i] * bv[j];
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
   double* out = part + ((size_t)b * n_chunks + c) * n_occ * n_occ;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int m = m0 + ty * 8 + i;
-    if (m >= n_occ) continue;
+  for (int i = 0; i < 4; ++i) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int n = n0 + tx * 8 + j;
-      if (n < n_occ) out[(size_t)m * n_occ + n] = acc[i][j];
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + qn + j * 16 + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + qm + i * 16 + lk + 4 * v;
+        if (m < n_occ && n < n_occ) out[(size_t)m * n_occ + n] = acc[i][j][v];
+      }
     }
   }
 }

@@ -131,6 +131,21 @@ def test_chi0_apply_long_cell_all_tile_modes(P, long_cell, precision, tile_y):
     h.close()
 
 
+@pytest.mark.parametrize("name", ["tiny", "si8"])
+def test_galerkin_guess_is_exact_inside_the_occupied_span(P, name):
+    """u = 1 makes every right-hand side -psi_n lie in span(psi): the Galerkin
+    guess (Gram contraction on the matrix cores) then solves each system up
+    to the orbitals' own eigen-residual (about 1e-10), so at a tolerance above
+    that COCG takes no iteration, and chi0 1 = 0 (charge conservation).  A
+    wrong contraction leaves O(1) residuals."""
+    c = sc.preset(name)
+    h = _handle(P, c, stern_tol=1e-8)
+    y, st = h.chi0_apply(49.36, torch.ones((2, c.N_d), dtype=torch.float64))
+    assert st["cocg_iters_total"] == 0, st
+    assert torch.abs(y).max().item() < 1e-12
+    h.close()
+
+
 def test_chi0_apply_invariants(P, tiny):
     h = _handle(P, tiny, stern_tol=1e-11)
     rng = np.random.default_rng(14)
