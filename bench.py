@@ -38,6 +38,11 @@ WORKLOADS = {
                 pts_per_step=8, desc="Si8-like cell, 24^3 grid, 16 orbitals"),
     "tiny": dict(preset="tiny", n_lanczos=8, tol=1e-6, stride=2, interp="tricubic", every=1,
                  pts_per_step=8, desc="tiny 12^3 cell, 4 orbitals"),
+    # largest configuration: 2 points x 8 frequencies = 16 start vectors per step
+    # (x alone is 41 GB); every 9th coarse point per axis
+    "si216": dict(preset="si216", n_lanczos=8, tol=1e-6, stride=2, interp="tricubic", every=9,
+                  pts_per_step=2, cpu_orbitals=2,
+                  desc="Si216-like 3x3x3 cell, 72^3 grid, 432 orbitals, 864 nonlocal projectors"),
 }
 
 
@@ -45,7 +50,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cocg_algorithmic_bytes(st: dict, N: int, precision: str) -> float:
+def nl_support_points(proj) -> int:
+    """Grid points gathered per projection of one vector: the support of each
+    group of consecutive projectors with identical support (as the library
+    groups them, at most 4 per group)."""
+    if proj is None:
+        return 0
+    import numpy as np
+    ptr, idx = proj["ptr"], proj["idx"]
+    total, q, n = 0, 0, len(ptr) - 1
+    while q < n:
+        a, b = ptr[q], ptr[q + 1]
+        k = 1
+        while k < 4 and q + k < n and ptr[q + k + 1] - ptr[q + k] == b - a and \
+                np.array_equal(idx[ptr[q + k]:ptr[q + k + 1]], idx[a:b]):
+            k += 1
+        total += int(b - a)
+        q += k
+    return total
+
+
+def cocg_algorithmic_bytes(st: dict, N: int, precision: str, nl_support: int = 0) -> float:
     """HBM bytes the batched Sternheimer launches must move.
 
     FP32+refine, per system: 80 B/pt per COCG iteration (sweep A reads r, p_old
@@ -56,9 +81,14 @@ def cocg_algorithmic_bytes(st: dict, N: int, precision: str) -> float:
     """
     if precision == "fp32_refine":
         per_pt = 80.0 * st["cocg_iters_total"] + 80.0 * st["refine_cycles"] + 40.0 * st["n_systems"]
+        # nonlocal projections: gather p (8 B) per support point and iteration,
+        # x64 (16 B) per residual sweep; the shared projector tables are not counted
+        nl = nl_support * (8.0 * st["cocg_iters_total"] +
+                           16.0 * (st["refine_cycles"] + st["n_systems"]))
     else:
         per_pt = 160.0 * st["cocg_iters_total"] + 48.0 * st["n_systems"]
-    return per_pt * N
+        nl = nl_support * 16.0 * (st["cocg_iters_total"] + st["n_systems"])
+    return per_pt * N + nl
 
 
 def source_sha():
@@ -108,7 +138,9 @@ def load_or_make_cell(sc, preset, cache):
         cell.psi, cell.eps = z["psi"], z["eps"]
         cell.gap, cell.eig_residual = float(z["gap"]), float(z["res"])
         return cell
-    cell = sc.preset(preset, device="cuda")
+    # the orbital solver reports progress on large cells (a long silent setup
+    # would look hung)
+    cell = sc.preset(preset, device="cuda", verbose=2 if preset == "si216" else False)
     if cache:
         np.savez(cache, psi=cell.psi, eps=cell.eps, gap=cell.gap, res=cell.eig_residual)
     return cell
@@ -137,7 +169,7 @@ def cpu_baseline(cell, cfg, omega, orbitals=8):
     from threadpoolctl import threadpool_limits
     import oracle as O
     with threadpool_limits(limits=1):
-        ham = O.Hamiltonian(cell.n, cell.L, cell.v_loc)
+        ham = O.Hamiltonian(cell.n, cell.L, cell.v_loc, proj=cell.proj)
         coul = O.Coulomb(cell.n, cell.L)
         j = int(cell.N_d // 2)
         q = np.zeros(cell.N_d)
@@ -222,6 +254,7 @@ def main():
     cfg = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
+    log(f"[bench] building the {cfg['preset']} cell")
     cell = load_or_make_cell(sc, cfg["preset"], args.orbital_cache)
     log(f"[bench] cell {cfg['preset']} n={cell.n} N_s={cell.n_occ} gap={cell.gap:.2e} "
         f"eig residual={cell.eig_residual:.1e} setup {time.perf_counter() - t0:.1f}s")
@@ -274,7 +307,8 @@ def main():
     value = n_points / elapsed
     tot = {k: sum(s[k] for s in stats) for k in ("n_systems", "cocg_iters_total", "refine_cycles",
                                                  "n_noconv", "n_breakdown")}
-    alg_bytes = cocg_algorithmic_bytes(tot, cell.N_d, args.precision)
+    nl_sup = nl_support_points(cell.proj)
+    alg_bytes = cocg_algorithmic_bytes(tot, cell.N_d, args.precision, nl_sup)
     achieved = alg_bytes / (cocg_ms * 1e-3) / 1e9
     traffic = pmc_traffic(args.workload) if args.precision == "fp32_refine" else None
     timing = h.last_cocg_timing()
@@ -289,7 +323,7 @@ def main():
         t64 = time.perf_counter() - t1
         extra["fp64_points_per_s"] = pps * 8 / t64
         extra["speedup_vs_fp64"] = value / extra["fp64_points_per_s"]
-        extra["fp64_cocg_gbps"] = cocg_algorithmic_bytes(st64, cell.N_d, "fp64") / (tm64["ms"] * 1e-3) / 1e9
+        extra["fp64_cocg_gbps"] = cocg_algorithmic_bytes(st64, cell.N_d, "fp64", nl_sup) / (tm64["ms"] * 1e-3) / 1e9
         h64.close()
         log(f"[bench] fp64 step: {t64:.2f}s iters/system {st64['cocg_iters_total'] / st64['n_systems']:.1f} "
             f"max {st64['cocg_iters_max']}")
@@ -308,7 +342,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         try:
-            cpu = cpu_baseline(cell, cfg, float(omega[4]))
+            cpu = cpu_baseline(cell, cfg, float(omega[4]), orbitals=cfg.get("cpu_orbitals", 8))
         except Exception as e:  # the baseline must not hide the GPU result
             log(f"[bench] cpu baseline failed: {e!r}")
 

@@ -279,6 +279,8 @@ def ks_orbitals(cell: Cell, n_buffer=None, tol=1e-10, degree=24, max_iter=600,
 
     X = orth(X)
     X, HX, ev = rayleigh_ritz(X)
+    if verbose and verbose >= 2:
+        print(f"  chefsi: {k} states on {N} points, initial subspace ready", flush=True)
     res = float("inf")
     for it in range(max_iter):
         a = float(ev[-1])          # filter out everything above the top Ritz value
@@ -299,7 +301,7 @@ def ks_orbitals(cell: Cell, n_buffer=None, tol=1e-10, degree=24, max_iter=600,
         X, HX, ev = rayleigh_ritz(X)
         R = HX[:nocc] - ev[:nocc, None] * X[:nocc]
         res = float(torch.max(torch.linalg.norm(R, dim=1)))
-        if verbose and it % 10 == 0:
+        if verbose and (it % 10 == 0 or verbose >= 2):
             print(f"  chefsi it {it}: max residual {res:.3e}", flush=True)
         if res <= tol:
             break
