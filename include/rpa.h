@@ -98,6 +98,8 @@ typedef struct {
   int64_t n_noconv;           /* solves that hit stern_maxit */
   int64_t n_breakdown;        /* COCG breakdowns + Lanczos truncations */
   double seconds;             /* host wall time of the call */
+  int64_t n_fp64_fallback;    /* RPA_FP32_REFINE solves finished by FP64 COCG after the
+                                 FP32 iteration stagnated, broke down or overflowed */
 } rpa_stats;
 
 /* Create a handle: copy V, psi (FP64 and FP32), eps to resident device

@@ -53,7 +53,7 @@ class Stats(ctypes.Structure):
         ("n_systems", ctypes.c_int64), ("cocg_iters_total", ctypes.c_int64),
         ("cocg_iters_max", ctypes.c_int64), ("refine_cycles", ctypes.c_int64),
         ("n_noconv", ctypes.c_int64), ("n_breakdown", ctypes.c_int64),
-        ("seconds", ctypes.c_double),
+        ("seconds", ctypes.c_double), ("n_fp64_fallback", ctypes.c_int64),
     ]
 
     def as_dict(self):

@@ -33,7 +33,8 @@ namespace {
 
 constexpr int R = kRadius;
 constexpr int QN = 2 * R + 1;
-constexpr int kMinGap = 4;   // fewest FP32 iterations between reliable updates
+constexpr int kMinGap = 4;     // fewest FP32 iterations between reliable updates
+constexpr int kMaxGap = 100;   // most FP32 iterations between true-residual checks
 
 template <typename T> struct V2;
 template <> struct V2<float> { typedef float2 t; };
@@ -711,6 +712,7 @@ __device__ __forceinline__ void record(const CocgArgs& a, int s, int its, int cy
   atomicAdd(&a.stats[2], (unsigned long long)cycles);
   if (status == 1) atomicAdd(&a.stats[3], 1ULL);
   if (status == 2) atomicAdd(&a.stats[4], 1ULL);
+  if (status == 3) atomicAdd(&a.stats[5], 1ULL);
 }
 
 // ---------------------------------------------------------------------------
@@ -835,6 +837,7 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, 
   double rnorm = sqrt(v4[0]);      // current residual estimate
   double rho_r = v4[2], rho_i = v4[3];
   int its = 0, updates = 0, status = 0;
+  bool failed = false;             // FP32 iteration produced a non-finite value
   if (bnorm == 0.0) {
     zero_sweep(N, x);
   } else {
@@ -860,6 +863,7 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, 
       double m2[2] = {ap.mu_re, ap.mu_im};
       if constexpr (NL) nl_project<float, float>(a.nl, pnew, coef32, m2[0], m2[1]);
       block_reduce<2>(m2, red);
+      if (!isfinite(m2[0]) || !isfinite(m2[1])) { failed = true; break; }
       if (fabs(m2[0]) + fabs(m2[1]) < 1e-300) { status = 2; break; }
       double al_r, al_i;
       cdiv(rho_r, rho_i, m2[0], m2[1], al_r, al_i);
@@ -872,7 +876,12 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, 
       dfresh = false;
       double rn = sqrt(u3[0]);
       double rho_nr = u3[1], rho_ni = u3[2];
-      if ((rn < delta * rmax && its - last_upd >= kMinGap) || rn <= thr) {
+      if (!isfinite(rn) || !isfinite(rho_nr) || !isfinite(rho_ni)) { failed = true; break; }
+      // reliable update when the recursive residual has dropped by delta, on
+      // apparent convergence, and at least every kMaxGap iterations (an FP32
+      // recursion that stalls above delta * rmax is caught there)
+      if ((rn < delta * rmax && its - last_upd >= kMinGap) || rn <= thr ||
+          its - last_upd >= kMaxGap) {
         // reliable update: x64 += d; r = b - A x64 in FP64 (stored rounded to FP32)
         fold_sweep(N, x, d);
         __syncthreads();
@@ -901,17 +910,21 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, 
       first = false;
       float2* t = pold; pold = pnew; pnew = t;
     }
-    if (!dfresh) {                 // fold a pending correction (maxit / breakdown exits)
+    if (!dfresh && !failed) {      // fold a pending correction (maxit / breakdown exits)
       fold_sweep(N, x, d);
       __syncthreads();
     }
-    if (status == 0 && !(rnorm <= thr)) status = 1;   // NaN residual is not convergence
+    // not converged in FP32 (maxit, stagnation, breakdown, non-finite values):
+    // x64 holds the last folded solution, which the FP64 launch continues from
+    if (failed || status != 0 || !(rnorm <= thr)) status = a.fail_list ? 3 : (status ? status : 1);
   }
-  if (threadIdx.x == 0) record(a, s, its, updates, status);
+  if (threadIdx.x == 0) {
+    record(a, s, its, updates, status);
+    if (status == 3) a.fail_list[atomicAdd(a.fail_count, 1)] = s;
+  }
 }
 
 // M: 0 = tile covers the whole plane, 1 = y halo with one slot per thread,
-// 2 = y halo with two slots per thread.  PITCH: LDS row pitch (>= nz + 2R).// M: 0 = tile covers the whole plane, 1 = y halo with one slot per thread,
 // 2 = y halo with two slots per thread.  PITCH: LDS row pitch (>= nz + 2R).
 // NL: with the nonlocal projector term (a separate kernel, so the
 // projector-free kernels carry none of its code or registers).
@@ -926,11 +939,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_cocg(CocgArgs a) {
   char* nlc = smem + lds_plane_bytes(g, PITCH, REFINE) + red_bytes(blockDim.x);
   __shared__ int s_item;
   int item = 0;
+  // the FP64 launch after an FP32 one takes the systems the latter handed over
+  const int n_items = a.n_items_dev ? uni(*a.n_items_dev) : a.n_items;
   if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
   __syncthreads();
   item = uni(s_item);
   __syncthreads();
-  while (item < a.n_items) {
+  while (item < n_items) {
     const int s = uni(a.order[item]);
     const int b = s / a.n_occ;
     const int live = a.active == nullptr ? 1 : uni(a.active[b]);

@@ -59,7 +59,8 @@ struct rpa_ctx {
 
   // workspaces
   DevBuf x64, slots, u64, racc, vtmp, tmpA, Q, alpha, beta, mlen, active, order, iters, cycles,
-      status, counter, stats, omega_b, pos_b, idx_b, gpart, G, dhat, partials, interp_m, shifts, fail;
+      status, counter, stats, omega_b, pos_b, idx_b, gpart, G, dhat, partials, interp_m, shifts, fail,
+      faillist;
   int interp_kind = -1, interp_stride = -1;
   int interp_dims[3] = {0, 0, 0};
   size_t allocated = 0;
@@ -292,7 +293,11 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
     r_ = upload_order_for(h, B, omega_host, s);
     if (r_ != RPA_OK) return r_;
   }
-  HIPCHK(h, launch_fill_i(P<int>(h->counter), 0, 1, s));
+  // counter[0]: work queue of the launch; with FP32 refinement counter[1]
+  // is the queue of the FP64 launch and counter[2] the number of systems
+  // handed to it (listed in faillist)
+  HIPCHK(h, launch_fill_i(P<int>(h->counter), 0, 3, s));
+  if (refine) ENSURE(h, h->faillist, (size_t)n_items * sizeof(int));
 
   const int bpc = h->slots_per_cu > 0 ? h->slots_per_cu
                                       : cocg_blocks_per_cu(h->geom, h->block, refine, h->nl.n_proj);
@@ -328,17 +333,30 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
   a.inner_tol = h->inner_tol;
   a.max_cycles = 0;
   a.nl = h->nl;
+  a.n_items_dev = nullptr;
+  a.fail_list = refine ? P<int>(h->faillist) : nullptr;
+  a.fail_count = refine ? P<int>(h->counter) + 2 : nullptr;
   const size_t shmem = cocg_shmem_bytes(h->geom, h->block, refine, h->nl.n_proj);
+  // FP64 COCG for the systems the FP32 launch handed over (usually none; its
+  // workgroups then exit at once), in the same slot memory
+  CocgArgs f = a;
+  f.order = P<int>(h->faillist);
+  f.n_items_dev = P<int>(h->counter) + 2;
+  f.counter = P<int>(h->counter) + 1;
+  f.fail_list = nullptr;
+  f.fail_count = nullptr;
+  f.slot_bytes = cocg_slot_bytes(h->geom, false);
+  const int grid64 = (int)std::max<long long>(1, std::min<long long>(grid, (long long)grid * sb / f.slot_bytes));
+  const size_t shmem64 = cocg_shmem_bytes(h->geom, h->block, false, h->nl.n_proj);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timing) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
     rpa_status es = cocg_events(h, &e0, &e1);
     if (es != RPA_OK) return es;
     HIPCHK(h, hipEventRecord(e0, s));
-    HIPCHK(h, launch_cocg(a, refine, grid, h->block, shmem, s));
-    HIPCHK(h, hipEventRecord(e1, s));
-  } else {
-    HIPCHK(h, launch_cocg(a, refine, grid, h->block, shmem, s));
   }
+  HIPCHK(h, launch_cocg(a, refine, grid, h->block, shmem, s));
+  if (refine) HIPCHK(h, launch_cocg(f, false, grid64, h->block, shmem64, s));
+  if (timing) HIPCHK(h, hipEventRecord(e1, s));
   h->last_grid = grid;
 
   ENSURE(h, h->racc, (size_t)B * N * sizeof(double));
@@ -394,6 +412,7 @@ rpa_status end_stats(rpa_ctx* h, hipStream_t s, rpa_stats* st, double t0, long l
     st->n_noconv = (int64_t)dv[3];
     st->n_breakdown = (int64_t)dv[4] + extra_breakdowns;
     st->seconds = now_s() - t0;
+    st->n_fp64_fallback = (int64_t)dv[5];
   }
   if (dv[3] > 0) return set_err(RPA_W_NOCONV, "some Sternheimer solves did not converge");
   if (dv[4] > 0 || extra_breakdowns > 0) return set_err(RPA_W_BREAKDOWN, "breakdown occurred");
@@ -600,8 +619,10 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
     gq.nx = p->n[0]; gq.ny = ny; gq.nz = nz; gq.ty = ty; gq.ntiles = ny / ty; gq.N = N;
     ARG_CHECK(geom_supported(gq), "n[2] must be <= 116");
     const int blk = ((ty * nz + 63) / 64) * 64;
+    // FP32 refinement also runs the FP64 kernel (for the systems it hands over)
     ARG_CHECK(p->n_proj < 0 ||
-              cocg_shmem_bytes(gq, blk, p->precision == RPA_FP32_REFINE, p->n_proj) <= 160 * 1024,
+              (cocg_shmem_bytes(gq, blk, p->precision == RPA_FP32_REFINE, p->n_proj) <= 160 * 1024 &&
+               cocg_shmem_bytes(gq, blk, false, p->n_proj) <= 160 * 1024),
               "projector coefficients and stencil planes exceed the 160 KiB of LDS");
   }
   NlHost nlh;
@@ -755,7 +776,7 @@ rpa_status rpa_destroy(rpa_handle h) {
   DevBuf* bufs[] = {&h->x64, &h->slots, &h->u64, &h->racc, &h->vtmp, &h->tmpA, &h->Q, &h->alpha,
                     &h->beta, &h->mlen, &h->active, &h->order, &h->iters, &h->cycles, &h->status,
                     &h->counter, &h->stats, &h->omega_b, &h->pos_b, &h->idx_b, &h->gpart, &h->G,
-                    &h->dhat, &h->partials, &h->interp_m, &h->shifts, &h->fail};
+                    &h->dhat, &h->partials, &h->interp_m, &h->shifts, &h->fail, &h->faillist};
   for (DevBuf* b : bufs) fr(b->p);
   drop_graphs(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -777,7 +798,7 @@ rpa_status rpa_release_workspace(rpa_handle h) {
   DevBuf* bufs[] = {&h->x64, &h->slots, &h->u64, &h->racc, &h->vtmp, &h->tmpA, &h->Q, &h->alpha,
                     &h->beta, &h->mlen, &h->active, &h->order, &h->iters, &h->cycles, &h->status,
                     &h->counter, &h->gpart, &h->G, &h->dhat, &h->partials, &h->shifts, &h->dres,
-                    &h->nlcoef};
+                    &h->nlcoef, &h->faillist};
   for (DevBuf* b : bufs) {
     if (b->p) {
       (void)hipFree(b->p);
@@ -1112,7 +1133,9 @@ rpa_status rpa_autotune(rpa_handle h, int32_t n_lanczos, int32_t probe_iters,
     gq.ty = t;
     gq.ntiles = ny / t;
     const int blk = ((t * nz + 63) / 64) * 64;
-    if (cocg_shmem_bytes(gq, blk, refine, h->nl.n_proj) > 160 * 1024) continue;
+    if (cocg_shmem_bytes(gq, blk, refine, h->nl.n_proj) > 160 * 1024 ||
+        cocg_shmem_bytes(gq, blk, false, h->nl.n_proj) > 160 * 1024)
+      continue;
     tys.push_back(t);
   }
   if (tys.empty()) return set_err(RPA_E_STATE, "no tile shape fits");

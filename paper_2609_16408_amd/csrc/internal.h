@@ -71,10 +71,13 @@ struct CocgArgs {
   char* slot_ws;               // per-workgroup workspaces
   long long slot_bytes;        // bytes per workspace
   int* counter;                // work counter, zero before launch
+  const int* n_items_dev;      // non-null: the item count is read from here (fallback launch)
+  int* fail_list;              // non-null (FP32 launch): systems handed to the FP64 launch
+  int* fail_count;             // their number, zero before launch
   int* out_iters;              // [n_items] by system id
   int* out_cycles;
   int* out_status;             // 0 ok, 1 noconv, 2 breakdown
-  unsigned long long* stats;   // [5]: iters total, iters max, cycles, noconv, breakdown
+  unsigned long long* stats;   // [6]: iters total, iters max, cycles, noconv, breakdown, fallbacks
   double tol;
   int maxit;
   double inner_tol;            // FP32 inner relative reduction

@@ -427,6 +427,28 @@ def test_energy_from_coarse_matches_oracle(P, tiny):
     h.close()
 
 
+def test_g_sweep_metrics_match_oracle(P, tiny):
+    """The interpolation-accuracy sweep: interpolation and frequency integration
+    of the GPU reference diagonal by the library, against the oracle's
+    interpolants and metric definitions applied to the same values."""
+    from paper_2609_16408_amd import gsweep
+    h = _handle(P, tiny, stern_tol=1e-8)
+    ref, rows, d_host = gsweep.g_sweep(h, tiny.n_atoms, tiny.dV, n_omega=4, n_lanczos=6)
+    om, w = O.frequency_rule(4)
+    c_direct = w @ d_host / (2 * math.pi)
+    assert abs(ref["E_c_per_atom"] - c_direct.sum() / tiny.n_atoms) < 1e-14
+    assert {(r["g"], r["kind"]) for r in rows} == {(g, k) for g in (2, 3, 4, 6) for k in gsweep.KINDS}
+    for r in rows:
+        idx = sc.coarse_points(tiny.n, r["g"])
+        e_o, fine_o = O.correlation_energy_from_coarse(d_host[:, idx], w, tiny.n, r["g"], r["kind"],
+                                                       tiny.dV)
+        dE, l1, ecr = O.interp_metrics(c_direct, fine_o * tiny.dV, tiny.n_atoms)
+        assert abs(r["E_c_per_atom"] - e_o / tiny.n_atoms) <= 1e-12, r
+        assert abs(r["dE_per_atom"] - dE) <= 1e-12 and abs(r["L1_per_atom"] - l1) <= 1e-12 * max(1, l1), r
+        assert 0 <= r["ECR"] <= 1 + 1e-12
+    h.close()
+
+
 def test_correlation_energy_tiny_matches_oracle(P, tiny, tiny_ops):
     """Algorithm 1 end to end at stride 6 with trilinear interpolation."""
     ham, coul = tiny_ops
@@ -458,6 +480,26 @@ def test_fp32_refine_matches_oracle(P, tiny, tiny_ops):
     ec_ref = O.correlation_energy_from_coarse(ref, w, tiny.n, 6, "trilinear", tiny.dV)[0]
     assert abs(ec - ec_ref) / tiny.n_atoms <= 1e-5
     h.close()
+
+
+def test_fp32_refine_hands_stalled_solves_to_fp64(P):
+    """Si8-like cell at the smallest frequency: some FP32 recursions stall or
+    break down (they once ran to stern_maxit or returned NaN).  Every value
+    must come out finite and converged, equal to the FP64 path within the
+    Sternheimer tolerance."""
+    c = sc.preset("si8")
+    om, _ = P.frequency_rule(8)
+    pts = np.arange(2048, 4096)
+    h32 = _handle(P, c, precision="fp32_refine", stern_tol=1e-6)
+    d32, st = h32.lanczos_energy_density(om[:1], pts, 8)
+    h32.close()
+    h64 = _handle(P, c, precision="fp64", stern_tol=1e-6)
+    d64, _ = h64.lanczos_energy_density(om[:1], pts, 8)
+    h64.close()
+    d32, d64 = d32.cpu().numpy(), d64.cpu().numpy()
+    assert np.isfinite(d32).all()
+    assert st["n_noconv"] == 0, st
+    assert np.abs(d32 - d64).max() <= 1e-5 * np.abs(d64).max(), (np.abs(d32 - d64).max(), st)
 
 
 # --- error paths -------------------------------------------------------------------------
