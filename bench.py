@@ -230,6 +230,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slots-per-cu", type=int, default=0)
     ap.add_argument("--tile-y", type=int, default=0)
+    ap.add_argument("--use-graph", action="store_true",
+                    help="replay each batch's kernel sequence as a captured HIP graph")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose tile rows and workgroups per CU with rpa_autotune first")
     ap.add_argument("--inner-tol", type=float, default=0.0,
                     help="reliable-update factor of the FP32 COCG (0: library default)")
     ap.add_argument("--orbital-cache", default="", help="npz file to reuse/save the orbitals")
@@ -272,9 +276,14 @@ def main():
     def make_handle(precision):
         return P.handle_for_cell(cell, precision=precision, stern_tol=cfg["tol"],
                                  stern_maxit=20000, batch=64, slots_per_cu=args.slots_per_cu,
-                                 tile_y=args.tile_y, inner_tol=args.inner_tol)
+                                 tile_y=args.tile_y, inner_tol=args.inner_tol,
+                                 use_graph=args.use_graph)
 
     h = make_handle(args.precision)
+    tuned = None
+    if args.autotune:
+        tuned = h.autotune(n_lanczos=cfg["n_lanczos"])
+        log(f"[bench] autotune: {tuned}")
     d_coarse = torch.zeros((8, coarse.size), dtype=torch.float64, device="cuda")
 
     def step(hd, i):
@@ -309,7 +318,8 @@ def main():
                                                  "n_noconv", "n_breakdown")}
     nl_sup = nl_support_points(cell.proj)
     alg_bytes = cocg_algorithmic_bytes(tot, cell.N_d, args.precision, nl_sup)
-    achieved = alg_bytes / (cocg_ms * 1e-3) / 1e9
+    # graph replay records no per-kernel events: no kernel rate then
+    achieved = alg_bytes / (cocg_ms * 1e-3) / 1e9 if cocg_ms > 0 else None
     traffic = pmc_traffic(args.workload) if args.precision == "fp32_refine" else None
     timing = h.last_cocg_timing()
 
@@ -364,12 +374,13 @@ def main():
                    "points_per_step": pps * 8, "coarse_stride": stride,
                    "interp": cfg["interp"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": alg_bytes / max(1, cocg_launches),
+                     "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": alg_bytes / cocg_launches if cocg_launches else None,
                      "kernel": "k_cocg (batched Sternheimer COCG)", "cocg_source_sha": source_sha(),
                      "launches": cocg_launches, "avg_launch_ms": cocg_ms / max(1, cocg_launches),
                      "grid": timing["grid"], "block": timing["block"], "tile_y": timing["tile_y"]},
         "cpu_baseline": cpu,
+        "launch": {"use_graph": bool(args.use_graph), "autotuned": tuned},
         "cocg": {"iters_per_system": tot["cocg_iters_total"] / max(1, tot["n_systems"]),
                  "refine_cycles_per_system": tot["refine_cycles"] / max(1, tot["n_systems"]),
                  "noconv": tot["n_noconv"], "E_c_partial": e_c},
