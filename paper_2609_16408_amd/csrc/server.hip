@@ -193,7 +193,12 @@ rpa_status rpa_server_add_cell(rpa_server S, const rpa_setup_params* p, int32_t*
     c->prm.proj_val = c->proj_val.data();
     c->prm.proj_gamma = c->proj_gamma.data();
   }
-  const uint64_t bytes = (uint64_t)c->N * 8 * (1 + (uint64_t)c->nocc);
+  uint64_t bytes = (uint64_t)c->N * 8 * (1 + (uint64_t)c->nocc);
+  if (p->n_proj > 0) {
+    // both projector layouts: indices, FP32 and FP64 values twice, point pointers
+    const uint64_t nnz = (uint64_t)p->proj_ptr[p->n_proj];
+    bytes += 2 * nnz * (4 + 4 + 8) + ((uint64_t)c->N + 1) * 4;
+  }
   if (S->prm.fake_executor_us == 0) {
     if (!p->v_loc || !p->psi) return RPA_E_ARG;
     if (hipMalloc((void**)&c->v, c->N * sizeof(double)) != hipSuccess ||

@@ -360,6 +360,22 @@ def test_graph_replay_matches_eager(P, tiny):
     graph.close()
 
 
+def test_graph_replay_fp32_with_projectors_matches_eager(P, tiny_nl):
+    """Graph capture of the FP32 sequence (persistent FP32 launch, FP64
+    follow-up launch, nonlocal kernels) against eager execution, bitwise."""
+    om = np.array([0.0203, 0.69])
+    pts = np.array([0, 31, 999, 1727, 640])
+    eager = _handle(P, tiny_nl, precision="fp32_refine", stern_tol=1e-8, batch=4)
+    graph = _handle(P, tiny_nl, precision="fp32_refine", stern_tol=1e-8, batch=4, use_graph=True)
+    for rep in range(3):
+        ref, _ = eager.lanczos_energy_density(om, pts, 5)
+        d, _ = graph.lanczos_energy_density(om, pts, 5)
+        assert torch.equal(d, ref), rep
+        torch.cuda.synchronize()
+    eager.close()
+    graph.close()
+
+
 def test_lanczos_short_runs_and_edge_points(P, tiny, tiny_ops):
     ham, coul = tiny_ops
     om = np.array([1.45])

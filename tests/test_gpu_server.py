@@ -56,3 +56,19 @@ def test_job_result_identical_alone_in_mix_and_direct(P, cells):
     d_direct, _ = h.lanczos_energy_density([0.31], pts_a, 4)
     h.close()
     assert torch.equal(d_direct[0], d_a_alone)
+
+
+def test_server_job_with_projectors_matches_direct_handle(P):
+    """A cell with nonlocal projectors goes through the serving loop unchanged."""
+    c = sc.preset("tiny", with_projectors=True, proj_seed=201)
+    pts = sc.coarse_points(c.n, 2)[:24]
+    s = P.Server(n_workers=2)
+    cid = s.add_cell(c.n, c.L, c.v_loc, c.psi, c.eps, precision="fp32_refine", stern_tol=1e-8,
+                     proj=c.proj)
+    d_a, info = s.wait(s.submit(cid, 0.69, pts, 4))
+    s.close()
+    assert info["status"] == 0
+    h = P.handle_for_cell(c, precision="fp32_refine", stern_tol=1e-8)
+    d_b, _ = h.lanczos_energy_density([0.69], pts, 4)
+    h.close()
+    assert torch.equal(d_b[0], d_a)
