@@ -201,7 +201,8 @@ def serving_run(P, sc, si64_cell, omega, log_fn, n_closed=12, n_open=20, warm=2)
     log_fn(f"[bench] serving pool ready in {time.perf_counter() - t0:.1f}s")
     n_lanczos, block = 3, 256
     jobs = serve.make_jobs(n_closed + 2 * n_open, cells, mix, omega, block, seed=4000)
-    secs, infos = serve.run_closed(server, cells, jobs[:n_closed], n_lanczos, depth=6)
+    mem = serve.DeviceMemoryPeak()
+    secs, infos = serve.run_closed(server, cells, jobs[:n_closed], n_lanczos, depth=6, mem=mem)
     sat = len(infos) / secs
     out = {"workload": "jobs of 256 coarse points at one frequency; 50% Si8-like (24^3, 16 orb), "
                        "30% Si16-like (24x24x48, 32 orb), 20% Si64-like (48^3, 128 orb); "
@@ -210,11 +211,17 @@ def serving_run(P, sc, si64_cell, omega, log_fn, n_closed=12, n_open=20, warm=2)
     log_fn(f"[bench] serving saturation {sat:.2f} jobs/s")
     for name, frac, lo in (("load_0.5", 0.5, n_closed), ("load_0.9", 0.9, n_closed + n_open)):
         secs, infos = serve.run_open(server, cells, jobs[lo:lo + n_open], n_lanczos,
-                                     rate=frac * sat, seed=4100 + int(10 * frac))
+                                     rate=frac * sat, seed=4100 + int(10 * frac), mem=mem)
         r = serve.summarize(infos, secs, warm=warm)
         r["points_per_s"] = n_open * block / secs
         out[name] = r
         log_fn(f"[bench] serving {name}: p50 {r['p50_latency_s']:.2f}s p99 {r['p99_latency_s']:.2f}s")
+    st = server.status()
+    # admission model (resident cells + admitted workspace estimates) and the
+    # device memory actually in use at job completions (whole GPU)
+    out["hbm_admitted_high_water_gb"] = st["high_water"] / 1e9
+    out["hbm_used_max_gb"] = mem.used_max / 1e9
+    out["hbm_budget_gb"] = 250.0
     server.close()
     return out
 

@@ -244,7 +244,12 @@ rpa_status rpa_server_submit(rpa_server s, int32_t cell_id, double omega, int32_
                              int64_t* job_id);
 /* Block until the job has finished; info (host) receives its record. */
 rpa_status rpa_server_wait(rpa_server s, int64_t job_id, rpa_job_info* info);
-rpa_status rpa_server_status(rpa_server s, int32_t* waiting, int32_t* running, uint64_t* in_use);
+/* Queue and memory state: jobs waiting and running, the workspace bytes of
+ * admitted jobs, and the high-water mark of resident cell data plus admitted
+ * workspaces since creation (the admission model's estimate).  Outputs are
+ * host pointers; any may be NULL. */
+rpa_status rpa_server_status(rpa_server s, int32_t* waiting, int32_t* running, uint64_t* in_use,
+                             uint64_t* high_water);
 /* Finish every queued job, stop the workers and free the cells. */
 rpa_status rpa_server_destroy(rpa_server s);
 

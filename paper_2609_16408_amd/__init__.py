@@ -106,7 +106,7 @@ _SIGS = {
     "rpa_server_add_cell": [_VP, ctypes.POINTER(SetupParams), _VP],
     "rpa_server_submit": [_VP, _I32, _D, _I32, _VP, _I32, _VP, _VP],
     "rpa_server_wait": [_VP, ctypes.c_int64, _VP],
-    "rpa_server_status": [_VP, _VP, _VP, _VP],
+    "rpa_server_status": [_VP, _VP, _VP, _VP, _VP],
     "rpa_server_destroy": [_VP],
 }
 
@@ -409,10 +409,10 @@ class Server:
 
     def status(self):
         w, r = ctypes.c_int32(), ctypes.c_int32()
-        u = ctypes.c_uint64()
-        _check(lib().rpa_server_status(self._h, ctypes.byref(w), ctypes.byref(r), ctypes.byref(u)),
-               "rpa_server_status")
-        return {"waiting": w.value, "running": r.value, "in_use": u.value}
+        u, hw = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().rpa_server_status(self._h, ctypes.byref(w), ctypes.byref(r), ctypes.byref(u),
+                                       ctypes.byref(hw)), "rpa_server_status")
+        return {"waiting": w.value, "running": r.value, "in_use": u.value, "high_water": hw.value}
 
     def close(self):
         if getattr(self, "_h", None):

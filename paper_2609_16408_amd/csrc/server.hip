@@ -75,6 +75,7 @@ struct rpa_server_s {
   int64_t next_id = 1;
   uint64_t in_use = 0;
   uint64_t resident = 0;
+  uint64_t high_water = 0;       // max of resident + in_use since creation
   int idle = 0;
   bool stop = false;
   std::vector<std::thread> workers;
@@ -112,6 +113,7 @@ void worker_main(rpa_server_s* S, int device) {
     }
     if (!job) break;
     S->in_use += job->footprint;
+    S->high_water = std::max(S->high_water, S->resident + S->in_use);
     job->info.t_start = now_s();
     lk.unlock();
 
@@ -220,6 +222,7 @@ rpa_status rpa_server_add_cell(rpa_server S, const rpa_setup_params* p, int32_t*
   std::lock_guard<std::mutex> lk(S->mu);
   // each worker holds its own resident copy once it has run a job of this cell
   S->resident += bytes * (uint64_t)(1 + S->prm.n_workers);
+  S->high_water = std::max(S->high_water, S->resident + S->in_use);
   S->cells.push_back(std::move(c));
   *cell_id = (int32_t)S->cells.size() - 1;
   return RPA_OK;
@@ -267,12 +270,14 @@ rpa_status rpa_server_wait(rpa_server S, int64_t job_id, rpa_job_info* info) {
   return RPA_OK;
 }
 
-rpa_status rpa_server_status(rpa_server S, int32_t* waiting, int32_t* running, uint64_t* in_use) {
+rpa_status rpa_server_status(rpa_server S, int32_t* waiting, int32_t* running, uint64_t* in_use,
+                             uint64_t* high_water) {
   if (!S) return RPA_E_ARG;
   std::lock_guard<std::mutex> lk(S->mu);
   if (waiting) *waiting = (int32_t)S->waiting.size();
   if (running) *running = S->prm.n_workers - S->idle - (S->stop ? S->prm.n_workers : 0);
   if (in_use) *in_use = S->in_use;
+  if (high_water) *high_water = S->high_water;
   return RPA_OK;
 }
 

@@ -27,7 +27,25 @@ def make_jobs(n_jobs, cells, mix, omegas, block, seed):
     return jobs
 
 
-def run_closed(server, cells, jobs, n_lanczos, depth):
+class DeviceMemoryPeak:
+    """Largest device memory in use (all allocations on the GPU, free memory
+    reported by the runtime), sampled when jobs complete; no-op without a GPU."""
+
+    def __init__(self):
+        self.used_max = 0
+        try:
+            import torch
+            self._info = torch.cuda.mem_get_info if torch.cuda.is_available() else None
+        except ImportError:
+            self._info = None
+
+    def sample(self):
+        if self._info is not None:
+            free, total = self._info()
+            self.used_max = max(self.used_max, total - free)
+
+
+def run_closed(server, cells, jobs, n_lanczos, depth, mem=None):
     """Keep `depth` jobs in flight; returns (seconds, infos)."""
     t0 = time.perf_counter()
     inflight, infos, k = [], [], 0
@@ -38,10 +56,12 @@ def run_closed(server, cells, jobs, n_lanczos, depth):
             k += 1
         _, info = server.wait(inflight.pop(0))
         infos.append(info)
+        if mem is not None:
+            mem.sample()
     return time.perf_counter() - t0, infos
 
 
-def run_open(server, cells, jobs, n_lanczos, rate, seed):
+def run_open(server, cells, jobs, n_lanczos, rate, seed, mem=None):
     """Submit at Poisson arrival times of the given rate (jobs/s); returns
     (seconds, infos) with latency = finish - submit."""
     rng = np.random.default_rng(seed)
@@ -55,7 +75,11 @@ def run_open(server, cells, jobs, n_lanczos, rate, seed):
         if dt > 0:
             time.sleep(dt)
         ids.append(server.submit(cells[c][0], w, pts, n_lanczos))
-    infos = [server.wait(j)[1] for j in ids]
+    infos = []
+    for j in ids:
+        infos.append(server.wait(j)[1])
+        if mem is not None:
+            mem.sample()
     return time.perf_counter() - t0, infos
 
 

@@ -80,3 +80,19 @@ def test_open_loop_driver_reports_latency_percentiles():
     s.close()
     r = serve.summarize(infos, secs)
     assert r["jobs"] == 12 and r["p99_latency_s"] >= r["p50_latency_s"] >= US * 1e-6
+
+
+def test_status_reports_admission_high_water():
+    """The high-water mark covers resident cell data plus every admitted job's
+    workspace estimate at its peak."""
+    s = P.Server(n_workers=2, fake_executor_us=20000)
+    cid = s.add_cell((24, 24, 24), (10.26,) * 3, None, None, np.linspace(-1, -0.5, 16),
+                     precision="fp32_refine")
+    idle = s.status()
+    assert idle["in_use"] == 0 and idle["high_water"] > 0     # resident data only
+    jobs = [s.submit(cid, 0.5, np.arange(64 * k, 64 * k + 64), 4) for k in range(4)]
+    infos = [s.wait(j)[1] for j in jobs]
+    st = s.status()
+    assert st["in_use"] == 0
+    assert st["high_water"] >= idle["high_water"] + max(i["footprint"] for i in infos)
+    s.close()
