@@ -71,7 +71,7 @@ def nl_support_points(proj) -> int:
 
 
 def cocg_algorithmic_bytes(st: dict, N: int, precision: str, nl_support: int = 0) -> float:
-    """HBM bytes the batched Sternheimer launches must move (see DESIGN.md).
+    """HBM bytes the batched Sternheimer launches must move.
 
     FP32+refine, per system: 80 B/pt per COCG iteration (sweep A reads r, p_old
     and writes p, q; sweep B reads p, q, r, d and writes d, r: 10 complex FP32
@@ -253,8 +253,9 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the per-point work "
-              "is independent, so N GPUs shard the (point, frequency) list with no communication "
-              "inside a frequency (see DESIGN.md).", file=sys.stderr)
+              "is independent, so N GPUs would shard the (point, frequency) list with no "
+              "communication inside a frequency and one all-gather of the coarse diagonals per "
+              "frequency.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

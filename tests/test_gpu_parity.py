@@ -518,6 +518,33 @@ def test_fp32_refine_hands_stalled_solves_to_fp64(P):
     assert np.abs(d32 - d64).max() <= 1e-5 * np.abs(d64).max(), (np.abs(d32 - d64).max(), st)
 
 
+@pytest.fixture(scope="module")
+def si64():
+    return sc.preset("si64", device="cuda")
+
+
+def test_si64_bench_configuration_fp32_matches_fp64(P, si64):
+    """Full Si64-like size in the launch configuration the benchmark times
+    (64 start vectors per launch: 8 points x 8 frequencies, N_l = 8, tol 1e-6):
+    every diagonal is <= 0, and the FP32 + refinement energy, extrapolated from
+    these points to the whole stride-2 coarse set, is within 1e-5 Ha/atom of
+    the FP64 path."""
+    c = si64
+    om, w = P.frequency_rule(8)
+    pts = sc.sublattice_points(c.n, 2, 3)[:8]
+    d = {}
+    for prec in ("fp32_refine", "fp64"):
+        h = _handle(P, c, precision=prec, stern_tol=1e-6, batch=64)
+        d[prec], st = h.lanczos_energy_density(om, pts, 8)
+        assert st["n_noconv"] == 0 and st["n_systems"] == 64 * c.n_occ * 8
+        h.close()
+    d32, d64 = d["fp32_refine"].cpu().numpy(), d["fp64"].cpu().numpy()
+    assert (d64 <= 0).all() and (d32 <= 0).all()
+    n_coarse = sc.coarse_points(c.n, 2).size
+    dE = (n_coarse / len(pts)) * float(np.abs(w @ (d32 - d64)).sum()) / (2 * math.pi) / c.n_atoms
+    assert dE <= 1e-5, dE
+
+
 # --- error paths -------------------------------------------------------------------------
 
 def test_error_paths(P, tiny):
