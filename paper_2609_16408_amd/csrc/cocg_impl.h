@@ -247,15 +247,17 @@ struct Marcher {
   }
 
   // PPS consecutive planes x, x+1 share one barrier: both are stored into
-  // their own buffers of the current set, then both are computed.
-  template <int PH>
+  // their own buffers of the current set, then both are computed.  TAIL: the
+  // block may end inside the pair (only the last block of a march).
+  template <int PH, bool TAIL>
   __device__ __forceinline__ void step(int x) {
     T2* set = buf0 + (size_t)(((x / PPS) & 1) * PPS) * bufs;
+    const bool second = PPS == 2 && (!TAIL || x + 1 < nx);
     put<PH>(set);
-    if (PPS == 2 && x + 1 < nx) put<PH + 1>(set + bufs);
+    if (second) put<PH + 1>(set + bufs);
     __syncthreads();
     point<PH>(x, set);
-    if (PPS == 2 && x + 1 < nx) point<PH + 1>(x + 1, set + bufs);
+    if (second) point<PH + 1>(x + 1, set + bufs);
   }
 
   template <int PH>
@@ -290,16 +292,25 @@ struct Marcher {
       pol.center((size_t)x * plane, col, c, mk2(sx, sy), ax[PH % PA]);
     }
     // refill the pipelines: the FIFO slot of plane x-R takes plane x+R+PF+1,
-    // the aux/halo slot of plane x takes plane x+PF+1
+    // the aux/halo slot of plane x takes plane x+PF+1.  The loads are issued
+    // unconditionally (past the last plane they re-read plane nx-1, and
+    // threads without a column read valid addresses whose values are never
+    // used): with no branch around them the compiler can count the loads in
+    // flight and wait only for the one a value comes from.
     const int xn = x + PF + 1;
-    if (xn < nx) {
-      if (own) {
-        fifo[PH % U] = pol.load((size_t)wrapx(xn + R, nx) * plane, col);
-        ax[PH % PA] = pol.aux((size_t)xn * plane, col);
-      }
+    const int xc = xn < nx ? xn : nx - 1;
+    fifo[PH % U] = pol.load((size_t)wrapx(xc + R, nx) * plane, col);
+    ax[PH % PA] = pol.aux((size_t)xc * plane, col);
 #pragma unroll
-      for (int h = 0; h < HS; ++h)
-        if (hv[h]) hq[h][PH % PA] = pol.load((size_t)xn * plane, hcol[h]);
+    for (int h = 0; h < HS; ++h) hq[h][PH % PA] = pol.load((size_t)xc * plane, hcol[h]);
+  }
+
+  // U planes from x; full blocks need no bounds checks between steps
+  template <int PH>
+  __device__ __forceinline__ void block_full(int x) {
+    if constexpr (PH < U) {
+      step<PH, false>(x);
+      block_full<PH + PPS>(x + PPS);
     }
   }
 
@@ -307,7 +318,7 @@ struct Marcher {
   __device__ __forceinline__ void block(int x) {
     if constexpr (PH < U) {
       if (x < nx) {
-        step<PH>(x);
+        step<PH, true>(x);
         block<PH + PPS>(x + PPS);
       }
     }
@@ -366,7 +377,9 @@ struct Marcher {
         for (int h = 0; h < HS; ++h)
           hq[h][j] = hv[h] ? pol.load((size_t)j * plane, hcol[h]) : zero2<T2>();
       }
-      for (int x = 0; x < nx; x += U) block<0>(x);
+      int x = 0;
+      for (; x + U <= nx; x += U) block_full<0>(x);
+      if (x < nx) block<0>(x);
       __syncthreads();
     }
   }
@@ -577,6 +590,51 @@ struct ApplyPol {
     (q + po)[c] = h;
     mu_re += (double)(pv.x * h.x - pv.y * h.y);
     mu_im += (double)(pv.x * h.y + pv.y * h.x);
+  }
+};
+
+// COCG sweep A without forming p as planes arrive: the stencil acts on r
+// only, and since A is linear, q = A p = A r + beta q_old with q_old = A p_old;
+// p = r + beta p_old and q are formed at the centre point from p_old and
+// q_old, which come through the centre pipeline like V.  Nothing is computed
+// from a value as soon as it is loaded, so the loads of later planes stay in
+// flight across steps.  q is updated in place (only its centre point is read).
+template <typename T>
+struct RecurPol {
+  typedef typename V2<T>::t T2;
+  const T2* r;
+  const T2* pold;
+  T2* pnew;
+  T2* q;
+  const T* v;
+  T c0, eps, om;
+  T br, bi;
+  bool first;                     // p = r, q = A r (p_old and q_old are not used)
+  double mu_re, mu_im;
+  static constexpr int kPF = 1;
+  struct Aux { T v; T2 p, q; };
+  __device__ Aux aux(size_t po, int c) const {
+    Aux a;
+    a.v = (v + po)[c];
+    a.p = (pold + po)[c];
+    a.q = (q + po)[c];
+    return a;
+  }
+  __device__ T2 load(size_t po, int c) const { return (r + po)[c]; }
+  __device__ void center(size_t po, int c, T2 rv, T2 nb, const Aux& ax) {
+    const T a = c0 + ax.v - eps;
+    T2 w, pv, qv;
+    w.x = a * rv.x + om * rv.y + nb.x;
+    w.y = a * rv.y - om * rv.x + nb.y;
+    pv.x = rv.x + br * ax.p.x - bi * ax.p.y;
+    pv.y = rv.y + br * ax.p.y + bi * ax.p.x;
+    qv.x = w.x + br * ax.q.x - bi * ax.q.y;
+    qv.y = w.y + br * ax.q.y + bi * ax.q.x;
+    if (first) { pv = rv; qv = w; }
+    (pnew + po)[c] = pv;
+    (q + po)[c] = qv;
+    mu_re += (double)(pv.x * qv.x - pv.y * qv.y);
+    mu_im += (double)(pv.x * qv.y + pv.y * qv.x);
   }
 };
 
@@ -850,17 +908,31 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, 
     double br = 0.0, bi = 0.0;
     bool first = true;             // p = r (no previous direction)
     bool dfresh = true;            // d holds nothing yet
+    bool exact_q = false;          // q = A p directly (after a residual replacement)
     float2* pold = pa;
     float2* pnew = pb;
     while (rnorm > thr) {
       if (its >= a.maxit) { status = 1; break; }
-      ApplyPol<float> ap;
-      ap.r = r; ap.pold = pold; ap.pnew = pnew; ap.q = q; ap.v = a.v32;
-      ap.c0 = a.c32.c0; ap.eps = (float)eps; ap.om = (float)om; ap.br = (float)br;
-      ap.bi = (float)bi; ap.first = first;
-      ap.mu_re = ap.mu_im = 0.0;
-      march<float, FULL, HS, PITCH>(g, a.c32, ap, reinterpret_cast<float2*>(smem), 0, g.ntiles);
-      double m2[2] = {ap.mu_re, ap.mu_im};
+      double m2[2];
+      if (exact_q) {
+        // bound the drift of the q recurrence: one sweep with p formed on load
+        ApplyPol<float> ap;
+        ap.r = r; ap.pold = pold; ap.pnew = pnew; ap.q = q; ap.v = a.v32;
+        ap.c0 = a.c32.c0; ap.eps = (float)eps; ap.om = (float)om; ap.br = (float)br;
+        ap.bi = (float)bi; ap.first = first;
+        ap.mu_re = ap.mu_im = 0.0;
+        march<float, FULL, HS, PITCH>(g, a.c32, ap, reinterpret_cast<float2*>(smem), 0, g.ntiles);
+        m2[0] = ap.mu_re; m2[1] = ap.mu_im;
+        exact_q = false;
+      } else {
+        RecurPol<float> ap;
+        ap.r = r; ap.pold = pold; ap.pnew = pnew; ap.q = q; ap.v = a.v32;
+        ap.c0 = a.c32.c0; ap.eps = (float)eps; ap.om = (float)om; ap.br = (float)br;
+        ap.bi = (float)bi; ap.first = first;
+        ap.mu_re = ap.mu_im = 0.0;
+        march<float, FULL, HS, PITCH>(g, a.c32, ap, reinterpret_cast<float2*>(smem), 0, g.ntiles);
+        m2[0] = ap.mu_re; m2[1] = ap.mu_im;
+      }
       if constexpr (NL) nl_project<float, float>(a.nl, pnew, coef32, m2[0], m2[1]);
       block_reduce<2>(m2, red);
       if (!isfinite(m2[0]) || !isfinite(m2[1])) { failed = true; break; }
@@ -901,6 +973,7 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, 
         rho_nr = w4[2];
         rho_ni = w4[3];
         rmax = rn;
+        exact_q = true;
         if (rn < 0.5 * best_true) { best_true = rn; no_gain = 0; }
         else if (++no_gain >= 4) { rnorm = rn; status = 1; break; }   // FP32 stagnation
       }
