@@ -914,7 +914,9 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, 
     while (rnorm > thr) {
       if (its >= a.maxit) { status = 1; break; }
       double m2[2];
-      if (exact_q) {
+      // the direct form also serves tiles with two halo slots per thread: there
+      // the recurrence form's larger centre pipeline is kept in scratch memory
+      if (exact_q || HS == 2) {
         // bound the drift of the q recurrence: one sweep with p formed on load
         ApplyPol<float> ap;
         ap.r = r; ap.pold = pold; ap.pnew = pnew; ap.q = q; ap.v = a.v32;
