@@ -37,6 +37,16 @@ is silent or ambiguous the reading taken is stated in the docstring:
   R11 (tricubic): separable 4-point Lagrange interpolation, periodic.
   R12 (Fourier): per-axis spectrum zero-padding, the even-length Nyquist
      coefficient split evenly between +k and -k.
+  R17 (Conclusions and Future Work, preconditioned Sternheimer solves):
+     left-preconditioned COCG with the shifted kinetic operator
+     M_n = -1/2 Lap_h + sigma_n, sigma_n = max(mean V_loc - eps_n, 1/4 Ha) - i w,
+     inverted exactly in the per-axis eigenbasis of Lap_h; the stopping rule
+     R8 is unchanged, so the solution tolerance is that of the plain solve.
+  R18 (Conclusions and Future Work, block Lanczos quadrature): block Gauss
+     quadrature from Q_1 = [e_j for a group of points]; block three-term
+     recurrence with thin QR, full reorthogonalisation as in R7, breakdown when
+     a diagonal entry of B_k falls to 1e-13 max|A_k|; d_j is the j-th diagonal
+     entry of E_1^T f(T) E_1 for the block tridiagonal T.
 """
 from __future__ import annotations
 
@@ -56,7 +66,8 @@ __all__ = [
     "lanczos_tridiag", "tridiag_quadrature", "f_rpa", "exact_diag_f",
     "frequency_rule", "interpolation_matrix_1d", "interpolate",
     "correlation_energy_from_coarse", "energy_density", "interp_metrics",
-    "coarse_index_set",
+    "coarse_index_set", "KineticPreconditioner", "kinetic_shift", "cocg_precond",
+    "block_lanczos", "block_tridiag", "block_quadrature", "energy_density_block",
 ]
 
 
@@ -468,4 +479,170 @@ def energy_density(ham: Hamiltonian, coul: Coulomb, psi, eps, omegas, points, n_
             if stats is not None and broke:
                 stats.setdefault("breakdowns", []).append((k, p))
             d[k, p] = tridiag_quadrature(a, b)
+    return d
+
+
+# -----------------------------------------------------------------------------
+# Next steps named in Conclusions and Future Work: preconditioned Sternheimer
+# solves and block Lanczos quadrature.  The paper names both without details;
+# the readings taken are R17 and R18 in the module docstring.
+# -----------------------------------------------------------------------------
+
+class KineticPreconditioner:
+    """M^-1 for the shifted kinetic operator M = -1/2 Lap_h + sigma (R17).
+
+    Lap_h is the FD Laplacian of H, diagonalised axis by axis (numpy eigh of
+    each periodic 1D D2, as for the Coulomb operator), so
+    M^-1 = (V_x (x) V_y (x) V_z) diag(1 / (kin + sigma)) (V_x (x) V_y (x) V_z)^T
+    with kin = -1/2 (lam_x + lam_y + lam_z) >= 0.  For complex sigma with a
+    positive real part it is complex symmetric and nonsingular, which COCG
+    needs.
+    """
+
+    def __init__(self, n, L, radius: int = 6):
+        self.n = tuple(n)
+        self.V = []
+        lams = []
+        for d in range(3):
+            lam, V = np.linalg.eigh(d2_periodic_1d(n[d], L[d] / n[d], radius))
+            self.V.append(V)
+            lams.append(lam)
+        self.kin = -0.5 * (lams[0][:, None, None] + lams[1][None, :, None] + lams[2][None, None, :])
+
+    def apply(self, r, sigma):
+        if not complex(sigma).real > 0.0:
+            raise ValueError("the kinetic preconditioner needs Re(sigma) > 0")
+        R = np.asarray(r).reshape(self.n)
+        Vx, Vy, Vz = self.V
+        C = np.einsum("ia,jb,kc,ijk->abc", Vx, Vy, Vz, R, optimize=True)
+        C = C / (self.kin + sigma)
+        return np.einsum("ia,jb,kc,abc->ijk", Vx, Vy, Vz, C, optimize=True).reshape(-1)
+
+
+def kinetic_shift(v_loc: np.ndarray, eps_n: float, omega: float, floor: float = 0.25) -> complex:
+    """sigma_n of the kinetic preconditioner (R17): max(mean(V_loc) - eps_n, floor) - i omega.
+
+    M then equals H - eps_n - i omega with the potential replaced by its mean;
+    the real part is clipped from below so that M stays well away from
+    singular for orbitals above the mean potential.
+    """
+    return complex(max(float(np.mean(v_loc)) - float(eps_n), float(floor)), -float(omega))
+
+
+def cocg_precond(apply_A, apply_Minv, b: np.ndarray, x0: np.ndarray, tol: float, maxit: int):
+    """COCG with a complex symmetric preconditioner M (R17).
+
+    z = M^-1 r, rho = r^T z, p = z + (rho'/rho) p; the stopping rule R8 stays
+    on the unpreconditioned residual.  With M = I every iterate equals that of
+    cocg.  Returns (x, iterations, status).
+    """
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return np.zeros_like(b, dtype=np.complex128), 0, "ok"
+    x = np.array(x0, dtype=np.complex128)
+    r = b - apply_A(x)
+    if np.linalg.norm(r) <= tol * bnorm:
+        return x, 0, "ok"
+    z = apply_Minv(r)
+    p = z.copy()
+    rho = r @ z
+    for it in range(1, maxit + 1):
+        q = apply_A(p)
+        mu = p @ q
+        if abs(mu) < 1e-300:
+            return x, it, "breakdown"
+        alpha = rho / mu
+        x = x + alpha * p
+        r = r - alpha * q
+        if np.linalg.norm(r) <= tol * bnorm:
+            return x, it, "ok"
+        z = apply_Minv(r)
+        rho_new = r @ z
+        if abs(rho_new) < 1e-300:
+            return x, it, "breakdown"
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    return x, maxit, "noconv"
+
+
+def block_lanczos(apply_A, Q1: np.ndarray, m: int, breakdown_rel: float = 1e-13):
+    """m block Lanczos steps on symmetric A from orthonormal columns Q1 (R18).
+
+    Block three-term recurrence A Q_k = Q_{k-1} B_{k-1}^T + Q_k A_k + Q_{k+1} B_k
+    with A_k = Q_k^T A Q_k (symmetrised) and Q_{k+1} B_k the thin QR of the
+    remainder, after two classical Gram-Schmidt passes against every stored
+    block.  Stops early (broke = True) when a diagonal entry of B_k is at most
+    breakdown_rel times the largest |A_k| entry.  apply_A maps N x b to N x b.
+    Returns (list of A_k, list of B_k, broke); len(B) = len(A) - 1.
+    """
+    Q = [np.array(Q1, dtype=np.float64)]
+    b = Q[0].shape[1]
+    A_blocks, B_blocks = [], []
+    Q_prev = np.zeros_like(Q[0])
+    B_prev = np.zeros((b, b))
+    broke = False
+    for k in range(m):
+        W = apply_A(Q[k])
+        Ak = Q[k].T @ W
+        Ak = 0.5 * (Ak + Ak.T)
+        W = W - Q[k] @ Ak - Q_prev @ B_prev.T
+        Qall = np.hstack(Q)
+        for _ in range(2):
+            W = W - Qall @ (Qall.T @ W)
+        A_blocks.append(Ak)
+        if k < m - 1:
+            Qn, R = np.linalg.qr(W)
+            scale = max(float(np.abs(a).max()) for a in A_blocks)
+            if float(np.abs(np.diag(R)).min()) <= breakdown_rel * scale:
+                broke = True
+                break
+            B_blocks.append(R)
+            Q_prev, B_prev = Q[k], R
+            Q.append(Qn)
+    return A_blocks, B_blocks, broke
+
+
+def block_tridiag(A_blocks, B_blocks) -> np.ndarray:
+    """Dense block tridiagonal T: diagonal A_k, below B_k, above B_k^T."""
+    b = A_blocks[0].shape[0]
+    k = len(A_blocks)
+    T = np.zeros((k * b, k * b))
+    for i, Ai in enumerate(A_blocks):
+        T[i * b:(i + 1) * b, i * b:(i + 1) * b] = Ai
+    for i, Bi in enumerate(B_blocks):
+        T[(i + 1) * b:(i + 2) * b, i * b:(i + 1) * b] = Bi
+        T[i * b:(i + 1) * b, (i + 1) * b:(i + 2) * b] = Bi.T
+    return T
+
+
+def block_quadrature(A_blocks, B_blocks) -> np.ndarray:
+    """diag(E_1^T f(T) E_1): the block Gauss estimate of e_j^T f(A) e_j (R18)."""
+    b = A_blocks[0].shape[0]
+    lam, U = np.linalg.eigh(block_tridiag(A_blocks, B_blocks))
+    return (U[:b, :] ** 2) @ f_rpa(lam)
+
+
+def energy_density_block(ham: Hamiltonian, coul: Coulomb, psi, eps, omegas, points, n_lanczos: int,
+                         block: int, tol: float = 1e-10, maxit: int = 20000, exact: bool = False,
+                         stats: dict | None = None):
+    """d[k, p] by block Lanczos quadrature over consecutive groups of `block` points (R18).
+
+    The start block of a group is [e_j for j in the group]; the last group may
+    be smaller.  block = 1 is the scalar quadrature of energy_density.
+    """
+    if block < 1:
+        raise ValueError("block must be >= 1")
+    points = list(points)
+    d = np.zeros((len(omegas), len(points)))
+    for k, w in enumerate(omegas):
+        A = nuhalf_chi0_nuhalf(ham, coul, psi, eps, w, tol=tol, maxit=maxit, exact=exact, stats=stats)
+        apply_block = lambda X, A=A: np.stack([A(X[:, c]) for c in range(X.shape[1])], axis=1)
+        for g0 in range(0, len(points), block):
+            grp = points[g0:g0 + block]
+            Q1 = np.zeros((ham.N, len(grp)))
+            Q1[grp, np.arange(len(grp))] = 1.0
+            Ab, Bb, broke = block_lanczos(apply_block, Q1, n_lanczos)
+            if stats is not None and broke:
+                stats.setdefault("breakdowns", []).append((k, g0))
+            d[k, g0:g0 + len(grp)] = block_quadrature(Ab, Bb)
     return d

@@ -417,3 +417,171 @@ def test_correlation_energy_g1_is_plain_sum():
     e_c, e_fine = O.correlation_energy_from_coarse(d, w, n, 1, "none", dV=0.125)
     assert abs(e_c - np.sum(w[:, None] * d) / (2 * np.pi)) < 1e-12
     assert abs(np.sum(e_fine) * 0.125 - e_c) < 1e-12
+
+
+# --- preconditioned Sternheimer solves (Conclusions and Future Work; reading R17) ---
+
+def test_kinetic_preconditioner_inverts_shifted_fd_laplacian(tiny_cell):
+    """M^-1 (-1/2 Lap_h + sigma) v = v, with Lap_h assembled as a sparse stencil."""
+    c = tiny_cell
+    pc = O.KineticPreconditioner(c.n, c.L)
+    lap = O.laplacian(c.n, c.L)
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal(c.N_d) + 1j * rng.standard_normal(c.N_d)
+    for sigma in (0.25, 0.3 - 0.02j, 1.7 - 3.2j):
+        Mv = -0.5 * (lap @ v) + sigma * v
+        back = pc.apply(Mv, sigma)
+        assert np.linalg.norm(back - v) <= 1e-12 * np.linalg.norm(v)
+    with pytest.raises(ValueError):
+        pc.apply(v, -0.1)
+
+
+def test_kinetic_shift_definition(tiny_cell):
+    c = tiny_cell
+    vbar = float(np.mean(c.v_loc))
+    assert O.kinetic_shift(c.v_loc, vbar - 0.7, 0.5) == complex(0.7, -0.5)
+    assert O.kinetic_shift(c.v_loc, vbar + 0.7, 0.5) == complex(0.25, -0.5)
+
+
+def test_preconditioned_cocg_with_identity_is_plain_cocg(tiny_cell, tiny_ops):
+    c = tiny_cell
+    ham, _ = tiny_ops
+    u = np.random.default_rng(5).standard_normal(c.N_d)
+    n, w = 2, 0.69
+    b = -c.psi[n] * u
+    z = c.eps[n] + 1j * w
+    A = lambda v: ham.apply(v) - z * v
+    x0 = O.galerkin_guess(c.psi, c.eps, n, b, w, c.dV)
+    x1, i1, s1 = O.cocg(A, b, x0, 1e-9, 20000)
+    x2, i2, s2 = O.cocg_precond(A, lambda r: r, b, x0, 1e-9, 20000)
+    assert (s1, i1) == (s2, i2) and s1 == "ok"
+    assert np.array_equal(x1, x2)
+
+
+@pytest.mark.parametrize("omega", [0.0203, 0.69])
+def test_preconditioned_cocg_matches_direct_solve_in_fewer_iterations(tiny_cell, tiny_ops, omega):
+    c = tiny_cell
+    ham, _ = tiny_ops
+    pc = O.KineticPreconditioner(c.n, c.L)
+    u = np.random.default_rng(5).standard_normal(c.N_d)
+    n = 3
+    b = -c.psi[n] * u
+    z = c.eps[n] + 1j * omega
+    A = lambda v: ham.apply(v) - z * v
+    x_dir = __import__("scipy.sparse.linalg", fromlist=["spsolve"]).spsolve(
+        ham.shifted_sparse(z), b.astype(complex))
+    x0 = O.galerkin_guess(c.psi, c.eps, n, b, omega, c.dV)
+    sigma = O.kinetic_shift(c.v_loc, c.eps[n], omega)
+    x, its, status = O.cocg_precond(A, lambda r: pc.apply(r, sigma), b, x0, 1e-10, 20000)
+    assert status == "ok"
+    # the stopping rule is on the unpreconditioned residual, recomputed here
+    assert np.linalg.norm(b - A(x)) <= 1.01e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - x_dir) <= 1e-7 * np.linalg.norm(x_dir)
+    _, its_plain, _ = O.cocg(A, b, x0, 1e-10, 20000)
+    assert its < its_plain / 2
+
+
+# --- block Lanczos quadrature (Conclusions and Future Work; reading R18) ----------
+
+def _onehot_block(N, pts):
+    Q = np.zeros((N, len(pts)))
+    Q[list(pts), np.arange(len(pts))] = 1.0
+    return Q
+
+
+def test_block_lanczos_with_one_column_is_scalar_lanczos():
+    A = _random_nsd(40, 7)
+    e = np.zeros(40)
+    e[5] = 1.0
+    for m in (1, 3, 6):
+        a, b, _ = O.lanczos_tridiag(lambda v: A @ v, e, m)
+        Ab, Bb, broke = O.block_lanczos(lambda X: A @ X, e[:, None], m)
+        assert not broke
+        assert np.allclose([x[0, 0] for x in Ab], a, rtol=0, atol=1e-13)
+        assert np.allclose([abs(x[0, 0]) for x in Bb], b, rtol=0, atol=1e-13)
+        assert abs(O.block_quadrature(Ab, Bb)[0] - O.tridiag_quadrature(a, b)) < 1e-13
+
+
+def test_block_gauss_quadrature_exact_to_degree_2m_minus_1():
+    """E_1^T T^p E_1 = Q_1^T A^p Q_1 for p <= 2m - 1, and not for p = 2m."""
+    A = _random_nsd(30, 8)
+    pts = (2, 11, 29)
+    Q1 = _onehot_block(30, pts)
+    m = 3
+    Ab, Bb, broke = O.block_lanczos(lambda X: A @ X, Q1, m)
+    assert not broke
+    T = O.block_tridiag(Ab, Bb)
+    assert np.array_equal(T, T.T)
+    b = len(pts)
+    Tp, Ap = np.eye(T.shape[0]), np.eye(30)
+    for p in range(0, 2 * m + 1):
+        lhs = Tp[:b, :b]
+        rhs = Q1.T @ Ap @ Q1
+        if p <= 2 * m - 1:
+            assert np.abs(lhs - rhs).max() <= 1e-11 * 3.0 ** p
+        else:
+            assert np.abs(lhs - rhs).max() > 1e-6
+        Tp, Ap = Tp @ T, Ap @ A
+
+
+def test_block_quadrature_exact_at_full_krylov_dimension():
+    A = _random_nsd(12, 9)
+    ref = O.exact_diag_f(A)
+    pts = (0, 5, 7)
+    Ab, Bb, broke = O.block_lanczos(lambda X: A @ X, _onehot_block(12, pts), 4)
+    assert not broke
+    assert np.abs(O.block_quadrature(Ab, Bb) - ref[list(pts)]).max() < 1e-12
+
+
+def test_block_quadrature_exact_at_full_dimension_on_a_stiff_spectrum():
+    """Eigenvalues from -1e-4 to -80: without reorthogonalisation the recurrence
+    loses orthogonality and T acquires spurious eigenvalues above 1."""
+    rng = np.random.default_rng(1)
+    N = 60
+    Q, _ = np.linalg.qr(rng.standard_normal((N, N)))
+    lam = -np.concatenate([np.logspace(-4, 0, N - 4), [20.0, 40.0, 60.0, 80.0]])
+    A = (Q * lam) @ Q.T
+    pts = (0, 7, 33)
+    Ab, Bb, broke = O.block_lanczos(lambda X: A @ X, _onehot_block(N, pts), 20)
+    assert not broke
+    ref = O.exact_diag_f(A)[list(pts)]
+    assert np.abs(O.block_quadrature(Ab, Bb) - ref).max() < 1e-12
+
+
+def test_block_quadrature_breakdown_on_invariant_subspace_is_exact():
+    """A start block inside a 4-dimensional invariant subspace closes after two blocks."""
+    A = np.zeros((10, 10))
+    A[:4, :4] = _random_nsd(4, 11)
+    A[4:, 4:] = _random_nsd(6, 12)
+    Ab, Bb, broke = O.block_lanczos(lambda X: A @ X, _onehot_block(10, (0, 1)), 5)
+    assert broke and len(Ab) == 2
+    ref = O.exact_diag_f(A)
+    assert np.abs(O.block_quadrature(Ab, Bb) - ref[[0, 1]]).max() < 1e-12
+
+
+def test_block_quadrature_is_equivariant_under_point_order():
+    A = _random_nsd(25, 13)
+    pts = [3, 17, 8, 21]
+    perm = [2, 0, 3, 1]
+    d = O.block_quadrature(*O.block_lanczos(lambda X: A @ X, _onehot_block(25, pts), 3)[:2])
+    dp = O.block_quadrature(*O.block_lanczos(lambda X: A @ X, _onehot_block(25, [pts[i] for i in perm]), 3)[:2])
+    assert np.abs(dp - d[perm]).max() < 1e-12
+
+
+def test_block_energy_density_on_tiny_cell(tiny_cell, tiny_ops, tiny_dense):
+    """block = 1 is the scalar path; groups of 3 + a ragged group of 1 converge
+    to the exact diagonal."""
+    c = tiny_cell
+    ham, coul = tiny_ops
+    ev, psi_all = tiny_dense
+    psi, eps = psi_all[: c.n_occ], ev[: c.n_occ]
+    omega = 0.69
+    pts = [0, 777, 1000, 1501]
+    d1 = O.energy_density(ham, coul, psi, eps, [omega], pts[:2], 4, tol=1e-11)
+    db1 = O.energy_density_block(ham, coul, psi, eps, [omega], pts[:2], 4, block=1, tol=1e-11)
+    assert np.abs(d1 - db1).max() < 1e-13
+    chi = O.chi0_sos(psi_all, ev, c.n_occ, omega, c.dV)
+    Nh = coul.dense_half()
+    dex = O.exact_diag_f(Nh @ chi @ Nh)[pts]
+    db = O.energy_density_block(ham, coul, psi, eps, [omega], pts, 12, block=3, tol=1e-11)[0]
+    assert np.abs(db - dex).max() < 1e-9 * np.abs(dex).max()
