@@ -178,6 +178,22 @@ rpa_status rpa_hamiltonian_apply(rpa_handle h, int32_t nvec, const double* shift
 rpa_status rpa_coulomb_apply(rpa_handle h, int32_t power, int32_t nvec, const double* x,
                              double* y, void* stream);
 
+/* Shifted kinetic preconditioner: y[v] = (-1/2 Lap_h + sigma_v)^-1 x[v], the
+ * inverse taken exactly in the per-axis eigenbasis of the same 12th-order
+ * FD Laplacian as in H (the Kronecker form of the Coulomb operator, with
+ * the diagonal 1/(kin + sigma_v) instead of the Coulomb one).  It is the
+ * building block of preconditioned Sternheimer solves, which the
+ * Conclusions and Future Work section names as a way to cut the COCG
+ * iteration counts; with sigma_v = max(mean V_loc - eps_n, 1/4) - i omega
+ * the preconditioner approximates H - eps_n - i omega.
+ * x, y: [dev] FP64 complex, planar per vector: [nvec][2][N_d] (the N_d real
+ * parts, then the N_d imaginary parts); y may alias x.  sigma_re, sigma_im:
+ * [host] [nvec].  RPA_E_ARG (nothing launched) unless every sigma is finite
+ * with a positive real part.  Uses the handle's transform workspaces. */
+rpa_status rpa_kinetic_precond_apply(rpa_handle h, int32_t nvec, const double* sigma_re,
+                                     const double* sigma_im, const double* x, double* y,
+                                     void* stream);
+
 /* Device time of the batched Sternheimer (COCG) launches of the last
  * chi0_apply / lanczos_energy_density / correlation_energy call (sum in ms,
  * measured with HIP events on the call's stream, and the launch count), or

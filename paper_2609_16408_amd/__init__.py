@@ -99,6 +99,7 @@ _SIGS = {
                            ctypes.POINTER(Stats), _VP],
     "rpa_hamiltonian_apply": [_VP, _I32, _VP, _VP, _VP, _VP, _I32, _VP],
     "rpa_coulomb_apply": [_VP, _I32, _I32, _VP, _VP, _VP],
+    "rpa_kinetic_precond_apply": [_VP, _I32, _VP, _VP, _VP, _VP, _VP],
     "rpa_last_cocg_timing": [_VP, _VP, _VP, _VP, _VP, _VP],
     "rpa_release_workspace": [_VP],
     "rpa_autotune": [_VP, _I32, _I32, ctypes.POINTER(TuneResult), _VP],
@@ -306,6 +307,26 @@ class Handle:
         _check(lib().rpa_coulomb_apply(self._h, int(power), x.shape[0], _ptr(x), _ptr(y),
                                        _stream(stream)), "rpa_coulomb_apply")
         return y
+
+    def kinetic_precond_apply(self, x, sigma, stream=None):
+        """(-1/2 Lap_h + sigma_v)^-1 x[v] for complex x [nvec][N_d]; sigma: nvec complex."""
+        t = self._torch
+        x = t.as_tensor(x).to(t.device("cuda")).reshape(-1, self.N)
+        nvec = x.shape[0]
+        sg = np.asarray(sigma, dtype=np.complex128).reshape(-1)
+        if sg.size == 1:
+            sg = np.full(nvec, sg[0])
+        if sg.size != nvec:
+            raise ValueError("one sigma per vector")
+        xp = t.stack([x.real, x.imag], dim=1).to(t.float64).contiguous() if x.is_complex() \
+            else t.stack([x.to(t.float64), t.zeros_like(x, dtype=t.float64)], dim=1).contiguous()
+        yp = t.empty_like(xp)
+        sr = np.ascontiguousarray(sg.real)
+        si = np.ascontiguousarray(sg.imag)
+        _check(lib().rpa_kinetic_precond_apply(self._h, nvec, sr.ctypes.data, si.ctypes.data,
+                                               _ptr(xp), _ptr(yp), _stream(stream)),
+               "rpa_kinetic_precond_apply")
+        return t.complex(yp[:, 0], yp[:, 1])
 
     def last_cocg_timing(self):
         ms = ctypes.c_double()

@@ -116,6 +116,8 @@ hipError_t launch_set_onehot(double* q, long long stride, const long long* idx, 
 // out dims equal in dims with d[axis] replaced by n_out.  trans: use M^T
 // (then M is (n_in x n_out)).  scale (nullable) multiplies the output
 // elementwise (length = output 3D size, broadcast over the batch).
+hipError_t launch_kin_scale(double* a, const double* kin, const double* sig_re,
+                            const double* sig_im, int B, long long N, hipStream_t s);
 hipError_t launch_axis(const double* in, double* out, int B, int d0, int d1, int d2, int axis,
                        int n_out, const double* M, bool trans, const double* scale, hipStream_t s);
 

@@ -67,6 +67,30 @@ __global__ void k_axis(const double* __restrict__ in, double* __restrict__ out, 
 }
 
 // ---------------------------------------------------------------------------
+// Complex diagonal solve in the eigenbasis of the FD Laplacian, the middle
+// step of the shifted kinetic preconditioner: vector b is stored planar
+// (N real parts, then N imaginary parts) and each mode o is divided by
+// kin[o] + sigma_b, kin >= 0 the kinetic eigenvalue, Re(sigma_b) > 0.
+__global__ void k_kin_scale(double* __restrict__ a, const double* __restrict__ kin,
+                            const double* __restrict__ sig_re, const double* __restrict__ sig_im,
+                            int B, long long N) {
+  const long long total = (long long)B * N;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long b = t / N;
+    const long long o = t - b * N;
+    double* re = a + b * 2 * N;
+    double* im = re + N;
+    const double dr = kin[o] + sig_re[b];
+    const double di = sig_im[b];
+    const double den = dr * dr + di * di;
+    const double xr = re[o], xi = im[o];
+    re[o] = (xr * dr + xi * di) / den;
+    im[o] = (xi * dr - xr * di) / den;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Galerkin projection, part 1: part[b][c][m][n] = sum_{r in chunk c} psi_m psi_n u_b,
 // a contraction over grid points on the FP64 matrix cores.  A 256-thread
 // workgroup owns a 128 x 128 output tile; each wave a 64 x 64 quadrant as
@@ -481,6 +505,12 @@ hipError_t launch_axis(const double* in, double* out, int B, int d0, int d1, int
   return hipGetLastError();
 }
 
+hipError_t launch_kin_scale(double* a, const double* kin, const double* sig_re,
+                            const double* sig_im, int B, long long N, hipStream_t s) {
+  hipLaunchKernelGGL(k_kin_scale, dim3(grid_for((long long)B * N, 256)), dim3(256), 0, s, a, kin,
+                     sig_re, sig_im, B, N);
+  return hipGetLastError();
+}
 hipError_t launch_gram(const double* psi, const double* u, int B, int n_occ, long long N,
                        int n_chunks, double* part, hipStream_t s) {
   const int nt = (n_occ + GT - 1) / GT;
