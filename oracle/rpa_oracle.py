@@ -265,13 +265,18 @@ def cocg(apply_A, b: np.ndarray, x0: np.ndarray, tol: float, maxit: int):
 
 
 def chi0_apply(ham: Hamiltonian, psi: np.ndarray, eps: np.ndarray, u: np.ndarray, omega: float,
-               tol: float = 1e-10, maxit: int = 20000, exact: bool = False, stats: dict | None = None):
+               tol: float = 1e-10, maxit: int = 20000, exact: bool = False, stats: dict | None = None,
+               precond: "KineticPreconditioner | None" = None, v_loc: np.ndarray | None = None):
     """r = chi0(i omega) u by the Sternheimer route (Eq. 4; Algorithm 1 inner loop).
 
     For each occupied n: solve (H - eps_n - i omega) dpsi_n = -psi_n (.) u by
     COCG from the Galerkin guess (or by a sparse direct solve when exact=True),
-    then accumulate r += 4 psi_n (.) Re dpsi_n.
+    then accumulate r += 4 psi_n (.) Re dpsi_n.  With `precond` (and the
+    local potential `v_loc` for its shift) the solves are preconditioned
+    COCG with the shifted kinetic operator (reading R17).
     """
+    if precond is not None and v_loc is None:
+        raise ValueError("the preconditioner shift needs v_loc")
     r = np.zeros(ham.N)
     for n in range(psi.shape[0]):
         b = -psi[n] * u
@@ -281,7 +286,12 @@ def chi0_apply(ham: Hamiltonian, psi: np.ndarray, eps: np.ndarray, u: np.ndarray
             its, status = 0, "ok"
         else:
             x0 = galerkin_guess(psi, eps, n, b, omega, ham.dV)
-            x, its, status = cocg(lambda v, z=z: ham.apply(v) - z * v, b, x0, tol, maxit)
+            if precond is None:
+                x, its, status = cocg(lambda v, z=z: ham.apply(v) - z * v, b, x0, tol, maxit)
+            else:
+                sigma = kinetic_shift(v_loc, eps[n], omega)
+                x, its, status = cocg_precond(lambda v, z=z: ham.apply(v) - z * v,
+                                              lambda r, sg=sigma: precond.apply(r, sg), b, x0, tol, maxit)
         if stats is not None:
             stats.setdefault("iters", []).append(its)
             if status != "ok":
