@@ -38,7 +38,7 @@ is silent or ambiguous the reading taken is stated in the docstring:
   R12 (Fourier): per-axis spectrum zero-padding, the even-length Nyquist
      coefficient split evenly between +k and -k.
   R17 (Conclusions and Future Work, preconditioned Sternheimer solves):
-     left-preconditioned COCG with the shifted kinetic operator
+     preconditioned COCG (z = M^-1 r, rho = r^T z) with the shifted kinetic operator
      M_n = -1/2 Lap_h + sigma_n, sigma_n = max(mean V_loc - eps_n, 1/4 Ha) - i w,
      inverted exactly in the per-axis eigenbasis of Lap_h; the stopping rule
      R8 is unchanged, so the solution tolerance is that of the plain solve.
