@@ -53,6 +53,9 @@ def test_null_handle_is_rejected():
     L = P.lib()
     st = L.interpolate(None, 1, 2, 1, None, None, None)
     assert st == P.RPA_E_ARG
+    sig = np.array([0.25])
+    st = L.rpa_kinetic_precond_apply(None, 1, sig.ctypes.data, sig.ctypes.data, None, None, None)
+    assert st == P.RPA_E_ARG
 
 
 @pytest.mark.parametrize("case,msg", [
