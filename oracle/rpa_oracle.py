@@ -68,6 +68,7 @@ __all__ = [
     "correlation_energy_from_coarse", "energy_density", "interp_metrics",
     "coarse_index_set", "KineticPreconditioner", "kinetic_shift", "cocg_precond",
     "block_lanczos", "block_tridiag", "block_quadrature", "energy_density_block",
+    "galerkin_space",
 ]
 
 
@@ -233,6 +234,16 @@ def galerkin_guess(psi: np.ndarray, eps: np.ndarray, n: int, b: np.ndarray, omeg
     return (c / (eps - eps[n] - 1j * omega)) @ psi
 
 
+def galerkin_space(psi: np.ndarray, eps: np.ndarray, psi_extra=None, eps_extra=None):
+    """Eigenpairs spanned by the Galerkin guess: the occupied ones, then any
+    further eigenpairs of H given (an extension of R9, not in the paper)."""
+    if (psi_extra is None) != (eps_extra is None):
+        raise ValueError("psi_extra and eps_extra go together")
+    if psi_extra is None:
+        return psi, eps
+    return np.vstack([psi, psi_extra]), np.concatenate([eps, eps_extra])
+
+
 def cocg(apply_A, b: np.ndarray, x0: np.ndarray, tol: float, maxit: int):
     """Conjugate Orthogonal CG for complex symmetric A (unconjugated u^T v).
 
@@ -266,17 +277,22 @@ def cocg(apply_A, b: np.ndarray, x0: np.ndarray, tol: float, maxit: int):
 
 def chi0_apply(ham: Hamiltonian, psi: np.ndarray, eps: np.ndarray, u: np.ndarray, omega: float,
                tol: float = 1e-10, maxit: int = 20000, exact: bool = False, stats: dict | None = None,
-               precond: "KineticPreconditioner | None" = None, v_loc: np.ndarray | None = None):
+               precond: "KineticPreconditioner | None" = None, v_loc: np.ndarray | None = None,
+               psi_extra: np.ndarray | None = None, eps_extra: np.ndarray | None = None):
     """r = chi0(i omega) u by the Sternheimer route (Eq. 4; Algorithm 1 inner loop).
 
     For each occupied n: solve (H - eps_n - i omega) dpsi_n = -psi_n (.) u by
     COCG from the Galerkin guess (or by a sparse direct solve when exact=True),
     then accumulate r += 4 psi_n (.) Re dpsi_n.  With `precond` (and the
     local potential `v_loc` for its shift) the solves are preconditioned
-    COCG with the shifted kinetic operator (reading R17).
+    COCG with the shifted kinetic operator (reading R17).  With `psi_extra`,
+    `eps_extra` (further eigenpairs of H above the occupied ones) the
+    Galerkin guess spans them too; the accumulation stays over the occupied
+    orbitals only.
     """
     if precond is not None and v_loc is None:
         raise ValueError("the preconditioner shift needs v_loc")
+    psi_g, eps_g = galerkin_space(psi, eps, psi_extra, eps_extra)
     r = np.zeros(ham.N)
     for n in range(psi.shape[0]):
         b = -psi[n] * u
@@ -285,7 +301,7 @@ def chi0_apply(ham: Hamiltonian, psi: np.ndarray, eps: np.ndarray, u: np.ndarray
             x = spla.spsolve(ham.shifted_sparse(z), b.astype(np.complex128))
             its, status = 0, "ok"
         else:
-            x0 = galerkin_guess(psi, eps, n, b, omega, ham.dV)
+            x0 = galerkin_guess(psi_g, eps_g, n, b, omega, ham.dV)
             if precond is None:
                 x, its, status = cocg(lambda v, z=z: ham.apply(v) - z * v, b, x0, tol, maxit)
             else:

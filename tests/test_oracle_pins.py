@@ -500,6 +500,34 @@ def test_preconditioned_sternheimer_chi0_equals_sum_over_states(tiny_cell, tiny_
         O.chi0_apply(ham, psi_all[: c.n_occ], ev[: c.n_occ], u, omega, precond=pc)
 
 
+def test_extended_galerkin_guess_keeps_chi0_and_cuts_iterations(tiny_cell, tiny_ops, tiny_dense):
+    """Unoccupied eigenpairs in the Galerkin guess change the start, not chi0 (Eq. 2)."""
+    c = tiny_cell
+    ham, _ = tiny_ops
+    ev, psi_all = tiny_dense
+    u = np.random.default_rng(22).standard_normal(c.N_d)
+    omega = 0.0203
+    ref = O.chi0_sos(psi_all, ev, c.n_occ, omega, c.dV) @ u
+    occ = slice(0, c.n_occ)
+    ext = slice(c.n_occ, c.n_occ + 24)
+    # the widened guess is exact on the whole widened span: no residual there
+    n = c.n_occ - 1
+    b = -psi_all[n] * u
+    z = ev[n] + 1j * omega
+    psi_g, eps_g = O.galerkin_space(psi_all[occ], ev[occ], psi_all[ext], ev[ext])
+    x0 = O.galerkin_guess(psi_g, eps_g, n, b, omega, c.dV)
+    r0 = b - (ham.apply(x0) - z * x0)
+    assert np.abs(c.dV * psi_all[: c.n_occ + 24] @ r0).max() < 1e-10 * np.linalg.norm(b)
+    st_e, st_0 = {}, {}
+    got = O.chi0_apply(ham, psi_all[occ], ev[occ], u, omega, tol=1e-11, stats=st_e,
+                       psi_extra=psi_all[ext], eps_extra=ev[ext])
+    O.chi0_apply(ham, psi_all[occ], ev[occ], u, omega, tol=1e-11, stats=st_0)
+    assert np.abs(got - ref).max() <= 1e-8 * np.abs(ref).max()
+    assert sum(st_e["iters"]) < sum(st_0["iters"])
+    with pytest.raises(ValueError):
+        O.chi0_apply(ham, psi_all[occ], ev[occ], u, omega, psi_extra=psi_all[ext])
+
+
 # --- block Lanczos quadrature (Conclusions and Future Work; reading R18) ----------
 
 def _onehot_block(N, pts):
