@@ -195,7 +195,12 @@ rpa_status rpa_server_add_cell(rpa_server S, const rpa_setup_params* p, int32_t*
     c->prm.proj_val = c->proj_val.data();
     c->prm.proj_gamma = c->proj_gamma.data();
   }
-  uint64_t bytes = (uint64_t)c->N * 8 * (1 + (uint64_t)c->nocc);
+  // The server keeps V and psi (FP64); each worker's rpa_setup keeps V in FP64
+  // and FP32, psi, eps, the nu^1/2, nu and kinetic diagonals and the three
+  // per-axis eigenbases.
+  const uint64_t server_copy = (uint64_t)c->N * 8 * (1 + (uint64_t)c->nocc);
+  uint64_t bytes = server_copy + (uint64_t)c->N * (4 + 3 * 8) + (uint64_t)c->nocc * 8;
+  for (int d = 0; d < 3; ++d) bytes += (uint64_t)p->n[d] * p->n[d] * 8;
   if (p->n_proj > 0) {
     // both projector layouts: indices, FP32 and FP64 values twice, point pointers
     const uint64_t nnz = (uint64_t)p->proj_ptr[p->n_proj];
@@ -221,7 +226,7 @@ rpa_status rpa_server_add_cell(rpa_server S, const rpa_setup_params* p, int32_t*
   }
   std::lock_guard<std::mutex> lk(S->mu);
   // each worker holds its own resident copy once it has run a job of this cell
-  S->resident += bytes * (uint64_t)(1 + S->prm.n_workers);
+  S->resident += server_copy + bytes * (uint64_t)S->prm.n_workers;
   S->high_water = std::max(S->high_water, S->resident + S->in_use);
   S->cells.push_back(std::move(c));
   *cell_id = (int32_t)S->cells.size() - 1;
