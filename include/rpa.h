@@ -180,19 +180,29 @@ rpa_status rpa_coulomb_apply(rpa_handle h, int32_t power, int32_t nvec, const do
 
 /* Shifted kinetic preconditioner: y[v] = (-1/2 Lap_h + sigma_v)^-1 x[v], the
  * inverse taken exactly in the per-axis eigenbasis of the same 12th-order
- * FD Laplacian as in H (the Kronecker form of the Coulomb operator, with
- * the diagonal 1/(kin + sigma_v) instead of the Coulomb one).  It is the
- * building block of preconditioned Sternheimer solves, which the
- * Conclusions and Future Work section names as a way to cut the COCG
- * iteration counts; with sigma_v = max(mean V_loc - eps_n, 1/4) - i omega
- * the preconditioner approximates H - eps_n - i omega.
- * x, y: [dev] FP64 complex, planar per vector: [nvec][2][N_d] (the N_d real
- * parts, then the N_d imaginary parts); y may alias x.  sigma_re, sigma_im:
- * [host] [nvec].  RPA_E_ARG (nothing launched) unless every sigma is finite
- * with a positive real part.  Uses the handle's transform workspaces. */
-rpa_status rpa_kinetic_precond_apply(rpa_handle h, int32_t nvec, const double* sigma_re,
+ * FD Laplacian as in H (Kronecker form, as for the Coulomb operator, with
+ * the diagonal 1/(kin + sigma_v)).  It is the building block of
+ * preconditioned Sternheimer solves, which the Conclusions and Future Work
+ * section names as a way to cut the COCG iteration counts; with
+ * sigma_v = max(mean V_loc - eps_n, 1/4) - i omega it approximates
+ * H - eps_n - i omega.
+ * A plan is independent of any rpa_handle.  create: n[3] (each in
+ * [7, 4096]) and L[3] > 0 (bohr), host; it uploads the 1D bases and the
+ * kinetic diagonal on `stream` and waits for them.  apply: x, y [dev] FP64
+ * complex, planar per vector: [nvec][2][N_d] (the N_d real parts, then the
+ * N_d imaginary parts); y may alias x; sigma_re, sigma_im [host] [nvec].
+ * The plan owns its workspaces (2 x 16 B x nvec x N_d, grown on demand) and
+ * serves one stream at a time.  Errors: RPA_E_ARG (nothing launched) for a
+ * bad grid, a null pointer or a sigma that is not finite with a positive
+ * real part; RPA_E_OOM; RPA_E_HIP.  These calls report by status only and do
+ * not set rpa_last_error. */
+typedef struct rpa_kinetic_precond_s* rpa_kinetic_precond;
+rpa_status rpa_kinetic_precond_create(const int32_t* n, const double* L, void* stream,
+                                      rpa_kinetic_precond* out);
+rpa_status rpa_kinetic_precond_apply(rpa_kinetic_precond p, int32_t nvec, const double* sigma_re,
                                      const double* sigma_im, const double* x, double* y,
                                      void* stream);
+rpa_status rpa_kinetic_precond_destroy(rpa_kinetic_precond p);
 
 /* Device time of the batched Sternheimer (COCG) launches of the last
  * chi0_apply / lanczos_energy_density / correlation_energy call (sum in ms,

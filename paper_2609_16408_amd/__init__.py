@@ -99,7 +99,9 @@ _SIGS = {
                            ctypes.POINTER(Stats), _VP],
     "rpa_hamiltonian_apply": [_VP, _I32, _VP, _VP, _VP, _VP, _I32, _VP],
     "rpa_coulomb_apply": [_VP, _I32, _I32, _VP, _VP, _VP],
+    "rpa_kinetic_precond_create": [_VP, _VP, _VP, _VP],
     "rpa_kinetic_precond_apply": [_VP, _I32, _VP, _VP, _VP, _VP, _VP],
+    "rpa_kinetic_precond_destroy": [_VP],
     "rpa_last_cocg_timing": [_VP, _VP, _VP, _VP, _VP, _VP],
     "rpa_release_workspace": [_VP],
     "rpa_autotune": [_VP, _I32, _I32, ctypes.POINTER(TuneResult), _VP],
@@ -137,10 +139,10 @@ def declared_symbols() -> list:
     return sorted(set(re.findall(r"^\s*(?:rpa_status|const char\*)\s+(\w+)\s*\(", txt, re.M)))
 
 
-def _check(status, what=""):
+def _check(status, what="", last_error=True):
     if status == RPA_OK:
         return status
-    msg = lib().rpa_last_error(None).decode()
+    msg = lib().rpa_last_error(None).decode() if last_error else f"status {status}"
     if status in (RPA_W_NOCONV, RPA_W_BREAKDOWN):
         warnings.warn(f"{what}: {msg}", RPAWarning, stacklevel=3)
         return status
@@ -220,6 +222,9 @@ class Handle:
         _check(lib().rpa_release_workspace(self._h), "rpa_release_workspace")
 
     def close(self):
+        if getattr(self, "_pc", None):
+            lib().rpa_kinetic_precond_destroy(self._pc)
+            self._pc = None
         if getattr(self, "_h", None):
             lib().rpa_destroy(self._h)
             self._h = None
@@ -323,9 +328,17 @@ class Handle:
         yp = t.empty_like(xp)
         sr = np.ascontiguousarray(sg.real)
         si = np.ascontiguousarray(sg.imag)
-        _check(lib().rpa_kinetic_precond_apply(self._h, nvec, sr.ctypes.data, si.ctypes.data,
+        if getattr(self, "_pc", None) is None:
+            n = np.ascontiguousarray(self.n, dtype=np.int32)
+            L = np.ascontiguousarray(self.L, dtype=np.float64)
+            pc = ctypes.c_void_p()
+            _check(lib().rpa_kinetic_precond_create(n.ctypes.data, L.ctypes.data, _stream(stream),
+                                                    ctypes.byref(pc)), "rpa_kinetic_precond_create",
+                   last_error=False)
+            self._pc = pc
+        _check(lib().rpa_kinetic_precond_apply(self._pc, nvec, sr.ctypes.data, si.ctypes.data,
                                                _ptr(xp), _ptr(yp), _stream(stream)),
-               "rpa_kinetic_precond_apply")
+               "rpa_kinetic_precond_apply", last_error=False)
         return t.complex(yp[:, 0], yp[:, 1])
 
     def last_cocg_timing(self):

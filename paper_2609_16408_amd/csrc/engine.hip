@@ -49,7 +49,6 @@ struct rpa_ctx {
   double* Vax[3] = {nullptr, nullptr, nullptr};   // per-axis eigenbasis [grid][mode]
   double* s_half = nullptr;
   double* s_full = nullptr;
-  double* kin = nullptr;             // -1/2 (lam_x + lam_y + lam_z) per mode
   StencilCoef<double> c64;
   StencilCoef<float> c32;
   Geom geom;
@@ -704,8 +703,7 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   if (!alloc((void**)&h->v64, N * sizeof(double)) || !alloc((void**)&h->v32, N * sizeof(float)) ||
       !alloc((void**)&h->psi64, (size_t)h->nocc * N * sizeof(double)) ||
       !alloc((void**)&h->eps_d, h->nocc * sizeof(double)) ||
-      !alloc((void**)&h->s_half, N * sizeof(double)) || !alloc((void**)&h->s_full, N * sizeof(double)) ||
-      !alloc((void**)&h->kin, N * sizeof(double)))
+      !alloc((void**)&h->s_half, N * sizeof(double)) || !alloc((void**)&h->s_full, N * sizeof(double)))
     return fail(RPA_E_OOM);
   for (int d = 0; d < 3; ++d)
     if (!alloc((void**)&h->Vax[d], (size_t)h->n[d] * h->n[d] * sizeof(double))) return fail(RPA_E_OOM);
@@ -735,13 +733,12 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
 
   std::vector<double> V[3], lam[3];
   for (int d = 0; d < 3; ++d) axis_basis(h->n[d], h->h[d], w, kRadius, V[d], lam[d]);
-  std::vector<double> sh((size_t)N), sf((size_t)N), kin((size_t)N);
+  std::vector<double> sh((size_t)N), sf((size_t)N);
   for (int i = 0; i < h->n[0]; ++i)
     for (int j = 0; j < h->n[1]; ++j)
       for (int k = 0; k < h->n[2]; ++k) {
         const size_t idx = ((size_t)i * h->n[1] + j) * h->n[2] + k;
         const double mu = -(lam[0][i] + lam[1][j] + lam[2][k]);
-        kin[idx] = 0.5 * mu;
         if (i == 0 && j == 0 && k == 0) { sh[idx] = 0.0; sf[idx] = 0.0; }
         else { sf[idx] = 4.0 * M_PI / mu; sh[idx] = std::sqrt(sf[idx]); }
       }
@@ -751,7 +748,6 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   if (e == hipSuccess) e = hipMemcpyAsync(h->eps_d, p->eps, h->nocc * sizeof(double), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(h->s_half, sh.data(), N * sizeof(double), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(h->s_full, sf.data(), N * sizeof(double), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(h->kin, kin.data(), N * sizeof(double), hipMemcpyHostToDevice, s);
   for (int d = 0; d < 3 && e == hipSuccess; ++d)
     e = hipMemcpyAsync(h->Vax[d], V[d].data(), V[d].size() * sizeof(double), hipMemcpyHostToDevice, s);
   for (size_t k = 0; k < nl_up.size() && e == hipSuccess; ++k)
@@ -773,7 +769,7 @@ rpa_status rpa_destroy(rpa_handle h) {
   if (!h) return RPA_OK;
   (void)hipDeviceSynchronize();
   auto fr = [](void* p) { if (p) (void)hipFree(p); };
-  fr(h->v64); fr(h->v32); fr(h->psi64); fr(h->eps_d); fr(h->s_half); fr(h->s_full); fr(h->kin);
+  fr(h->v64); fr(h->v32); fr(h->psi64); fr(h->eps_d); fr(h->s_half); fr(h->s_full);
   for (void* m : h->nl_mem) fr(m);
   fr(h->nlcoef.p);
   for (int d = 0; d < 3; ++d) fr(h->Vax[d]);
@@ -842,38 +838,6 @@ rpa_status rpa_hamiltonian_apply(rpa_handle h, int32_t nvec, const double* shift
   h->cocg_ms_total = ms;
   h->cocg_launches = 1;
   h->last_grid = h->geom.ntiles * nvec;
-  return RPA_OK;
-}
-
-rpa_status rpa_kinetic_precond_apply(rpa_handle h, int32_t nvec, const double* sigma_re,
-                                     const double* sigma_im, const double* x, double* y,
-                                     void* stream) {
-  rpa_status u = usable(h);
-  if (u != RPA_OK) return u;
-  ARG_CHECK(nvec >= 1 && sigma_re && sigma_im && x && y, "bad arguments");
-  for (int b = 0; b < nvec; ++b)
-    ARG_CHECK(std::isfinite(sigma_re[b]) && std::isfinite(sigma_im[b]) && sigma_re[b] > 0.0,
-              "sigma must be finite with a positive real part");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const int B = 2 * nvec;  // real and imaginary halves transform as separate real fields
-  const size_t bytes = (size_t)B * h->N * sizeof(double);
-  ENSURE(h, h->tmpA, bytes);
-  ENSURE(h, h->vtmp, bytes);
-  ENSURE(h, h->shifts, 2 * (size_t)nvec * sizeof(double));
-  HIPCHK(h, hipMemcpyAsync(h->shifts.p, sigma_re, nvec * sizeof(double), hipMemcpyHostToDevice, s));
-  HIPCHK(h, hipMemcpyAsync(P<double>(h->shifts) + nvec, sigma_im, nvec * sizeof(double),
-                           hipMemcpyHostToDevice, s));
-  double* a = P<double>(h->tmpA);
-  double* b = P<double>(h->vtmp);
-  const int* n = h->n;
-  HIPCHK(h, launch_axis(x, a, B, n[0], n[1], n[2], 0, n[0], h->Vax[0], true, nullptr, s));
-  HIPCHK(h, launch_axis(a, b, B, n[0], n[1], n[2], 1, n[1], h->Vax[1], true, nullptr, s));
-  HIPCHK(h, launch_axis(b, a, B, n[0], n[1], n[2], 2, n[2], h->Vax[2], true, nullptr, s));
-  HIPCHK(h, launch_kin_scale(a, h->kin, P<double>(h->shifts), P<double>(h->shifts) + nvec, nvec,
-                             h->N, s));
-  HIPCHK(h, launch_axis(a, b, B, n[0], n[1], n[2], 2, n[2], h->Vax[2], false, nullptr, s));
-  HIPCHK(h, launch_axis(b, a, B, n[0], n[1], n[2], 1, n[1], h->Vax[1], false, nullptr, s));
-  HIPCHK(h, launch_axis(a, y, B, n[0], n[1], n[2], 0, n[0], h->Vax[0], false, nullptr, s));
   return RPA_OK;
 }
 

@@ -196,10 +196,10 @@ rpa_status rpa_server_add_cell(rpa_server S, const rpa_setup_params* p, int32_t*
     c->prm.proj_gamma = c->proj_gamma.data();
   }
   // The server keeps V and psi (FP64); each worker's rpa_setup keeps V in FP64
-  // and FP32, psi, eps, the nu^1/2, nu and kinetic diagonals and the three
-  // per-axis eigenbases.
+  // and FP32, psi, eps, the nu^1/2 and nu diagonals and the three per-axis
+  // eigenbases.
   const uint64_t server_copy = (uint64_t)c->N * 8 * (1 + (uint64_t)c->nocc);
-  uint64_t bytes = server_copy + (uint64_t)c->N * (4 + 3 * 8) + (uint64_t)c->nocc * 8;
+  uint64_t bytes = server_copy + (uint64_t)c->N * (4 + 2 * 8) + (uint64_t)c->nocc * 8;
   for (int d = 0; d < 3; ++d) bytes += (uint64_t)p->n[d] * p->n[d] * 8;
   if (p->n_proj > 0) {
     // both projector layouts: indices, FP32 and FP64 values twice, point pointers

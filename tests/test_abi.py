@@ -58,6 +58,18 @@ def test_null_handle_is_rejected():
     assert st == P.RPA_E_ARG
 
 
+@pytest.mark.parametrize("n,L", [((5, 12, 12), (1.0, 1.0, 1.0)), ((12, 12, 5000), (1.0, 1.0, 1.0)),
+                                 ((12, 12, 12), (1.0, 0.0, 1.0)), ((12, 12, 12), (1.0, float("nan"), 1.0))])
+def test_kinetic_precond_create_rejects_bad_grids_without_a_gpu(n, L):
+    nn = np.ascontiguousarray(n, dtype=np.int32)
+    LL = np.ascontiguousarray(L, dtype=np.float64)
+    out = ctypes.c_void_p()
+    assert P.lib().rpa_kinetic_precond_create(nn.ctypes.data, LL.ctypes.data, None,
+                                              ctypes.byref(out)) == P.RPA_E_ARG
+    assert not out.value
+    assert P.lib().rpa_kinetic_precond_destroy(None) == P.RPA_OK
+
+
 @pytest.mark.parametrize("case,msg", [
     ("idx", b"proj_idx out of range"), ("ptr", b"non-decreasing"), ("count", b"n_proj"),
     ("null", b"required"), ("gamma", b"proj_gamma must be finite")])

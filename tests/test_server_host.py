@@ -42,7 +42,7 @@ def test_admission_respects_the_hbm_budget():
     fp = s0.wait(s0.submit(cid0, 0.5, np.arange(16), 4))[1]["footprint"]
     s0.close()
     N = 24 ** 3
-    worker = N * 8 * 17 + N * (4 + 3 * 8) + 16 * 8 + 3 * 24 * 24 * 8   # what rpa_setup keeps
+    worker = N * 8 * 17 + N * (4 + 2 * 8) + 16 * 8 + 3 * 24 * 24 * 8   # what rpa_setup keeps
     resident = N * 8 * 17 + 3 * worker       # server's V + 16 orbitals, 3 worker copies
     s, cid = _server(3, budget=resident + int(1.5 * fp))   # room for one job at a time
     ids = [s.submit(cid, 0.5, np.arange(16), 4) for _ in range(4)]
