@@ -88,6 +88,13 @@ typedef struct {
                                  launch sequence (all Lanczos steps) into a hipGraph
                                  and replays it for later batches of the same size;
                                  per-launch COCG timing is then not recorded */
+  int32_t fp32_maxit;         /* RPA_FP32_REFINE: FP32 COCG iterations a solve may take
+                                 before it is handed to the FP64 COCG, which continues
+                                 from the last folded FP64 solution with a budget of
+                                 stern_maxit iterations; 0 = stern_maxit */
+  double lanczos_breakdown;   /* Lanczos breakdown threshold (Algorithm 1 recurrence):
+                                 T is truncated at the first beta_k <= lanczos_breakdown *
+                                 max_i |alpha_i|, k < N_l; in [0, 1), 0 = 1e-13 */
 } rpa_setup_params;
 
 typedef struct {
@@ -173,6 +180,15 @@ rpa_status rpa_hamiltonian_apply(rpa_handle h, int32_t nvec, const double* shift
                                  const double* shift_im, const void* x, void* y,
                                  int32_t precision, void* stream);
 
+/* The Sternheimer solutions themselves (Eq. 4; Implementation section):
+ * x[v][n] solves (H - eps_n - i omega) x = -psi_n (.) u[v] by COCG from the
+ * Galerkin-projection guess, to the handle's stopping rule and precision --
+ * the solves chi0_apply accumulates.  u: [dev] FP64 [nvec][N_d];
+ * x: [dev] FP64 complex interleaved (re, im) [nvec][n_occ][N_d][2].  For
+ * checking solves against their true residuals; omega > 0. */
+rpa_status rpa_sternheimer_solve(rpa_handle h, double omega, int32_t nvec, const double* u,
+                                 double* x, rpa_stats* st, void* stream);
+
 /* y[v] = nu^(power/2) x[v], power 1 (nu^1/2) or 2 (nu); Kronecker form.
  * x, y: [dev] FP64 [nvec][N_d]. */
 rpa_status rpa_coulomb_apply(rpa_handle h, int32_t power, int32_t nvec, const double* x,
@@ -211,6 +227,23 @@ rpa_status rpa_kinetic_precond_destroy(rpa_kinetic_precond p);
  * output pointer may be NULL.  For measurement only. */
 rpa_status rpa_last_cocg_timing(rpa_handle h, double* ms, int32_t* launches, int32_t* grid,
                                 int32_t* block, int32_t* tile_y);
+
+/* Per-frequency COCG iteration statistics of the last chi0_apply or
+ * lanczos_energy_density call (the quantities of the paper's iteration
+ * tables in the Performance section: mean, standard deviation, minimum and
+ * maximum iterations per Sternheimer solve at each frequency).  One entry
+ * per frequency argument of the call (omega[k] of lanczos_energy_density,
+ * the single omega of chi0_apply), in that order: omega, the number of
+ * solves, and their iteration counts' mean, standard deviation
+ * (population), minimum and maximum.  A solve handed from FP32 to FP64 COCG
+ * counts once, with the iterations of both.  Outputs are [host] arrays of at
+ * least `cap` entries (any may be NULL); n_out receives the number of
+ * entries (also when it exceeds cap; then only cap are filled).  The
+ * statistics were read back when the call returned: this synchronises
+ * nothing. */
+rpa_status rpa_last_iteration_stats(rpa_handle h, int32_t cap, double* omega, int64_t* count,
+                                    double* mean, double* stdev, int64_t* min_iters,
+                                    int64_t* max_iters, int32_t* n_out);
 
 /* Launch-shape tuning (the handle's tile rows, workgroups per CU and start
  * vectors per launch).  Each candidate shape -- the whole (y, z) plane if it

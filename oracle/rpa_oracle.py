@@ -278,7 +278,8 @@ def cocg(apply_A, b: np.ndarray, x0: np.ndarray, tol: float, maxit: int):
 def chi0_apply(ham: Hamiltonian, psi: np.ndarray, eps: np.ndarray, u: np.ndarray, omega: float,
                tol: float = 1e-10, maxit: int = 20000, exact: bool = False, stats: dict | None = None,
                precond: "KineticPreconditioner | None" = None, v_loc: np.ndarray | None = None,
-               psi_extra: np.ndarray | None = None, eps_extra: np.ndarray | None = None):
+               psi_extra: np.ndarray | None = None, eps_extra: np.ndarray | None = None,
+               orbitals=None):
     """r = chi0(i omega) u by the Sternheimer route (Eq. 4; Algorithm 1 inner loop).
 
     For each occupied n: solve (H - eps_n - i omega) dpsi_n = -psi_n (.) u by
@@ -288,13 +289,15 @@ def chi0_apply(ham: Hamiltonian, psi: np.ndarray, eps: np.ndarray, u: np.ndarray
     COCG with the shifted kinetic operator (reading R17).  With `psi_extra`,
     `eps_extra` (further eigenpairs of H above the occupied ones) the
     Galerkin guess spans them too; the accumulation stays over the occupied
-    orbitals only.
+    orbitals only.  With `orbitals` (indices n) only those solves are done and
+    accumulated: the sum over n of Algorithm 1 split into parts, which sum to
+    the full result (the Galerkin guess still spans every occupied orbital).
     """
     if precond is not None and v_loc is None:
         raise ValueError("the preconditioner shift needs v_loc")
     psi_g, eps_g = galerkin_space(psi, eps, psi_extra, eps_extra)
     r = np.zeros(ham.N)
-    for n in range(psi.shape[0]):
+    for n in (range(psi.shape[0]) if orbitals is None else orbitals):
         b = -psi[n] * u
         z = eps[n] + 1j * omega
         if exact:
@@ -493,17 +496,21 @@ def interp_metrics(d_direct: np.ndarray, d_interp: np.ndarray, n_atoms: int = 1)
 # -----------------------------------------------------------------------------
 
 def energy_density(ham: Hamiltonian, coul: Coulomb, psi, eps, omegas, points, n_lanczos: int,
-                   tol: float = 1e-10, maxit: int = 20000, exact: bool = False, stats: dict | None = None):
-    """d[k, p] = [f(T_m)]_11 from q_1 = e_{points[p]} at omega_k (Algorithm 1)."""
+                   tol: float = 1e-10, maxit: int = 20000, exact: bool = False, stats: dict | None = None,
+                   breakdown_rel: float = 1e-13):
+    """d[k, p] = [f(T_m)]_11 from q_1 = e_{points[p]} at omega_k (Algorithm 1);
+    breakdown_rel is the truncation threshold of reading R7."""
     d = np.zeros((len(omegas), len(points)))
     for k, w in enumerate(omegas):
         A = nuhalf_chi0_nuhalf(ham, coul, psi, eps, w, tol=tol, maxit=maxit, exact=exact, stats=stats)
         for p, j in enumerate(points):
             q1 = np.zeros(ham.N)
             q1[j] = 1.0
-            a, b, broke = lanczos_tridiag(A, q1, n_lanczos)
-            if stats is not None and broke:
-                stats.setdefault("breakdowns", []).append((k, p))
+            a, b, broke = lanczos_tridiag(A, q1, n_lanczos, breakdown_rel=breakdown_rel)
+            if stats is not None:
+                stats.setdefault("lanczos_len", []).append(len(a))
+                if broke:
+                    stats.setdefault("breakdowns", []).append((k, p))
             d[k, p] = tridiag_quadrature(a, b)
     return d
 

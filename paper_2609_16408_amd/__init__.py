@@ -44,7 +44,8 @@ class SetupParams(ctypes.Structure):
         ("stern_maxit", ctypes.c_int32), ("batch", ctypes.c_int32),
         ("hbm_budget", ctypes.c_uint64), ("tile_y", ctypes.c_int32),
         ("slots_per_cu", ctypes.c_int32), ("inner_tol", ctypes.c_double),
-        ("use_graph", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32), ("fp32_maxit", ctypes.c_int32),
+        ("lanczos_breakdown", ctypes.c_double),
     ]
 
 
@@ -103,6 +104,8 @@ _SIGS = {
     "rpa_kinetic_precond_apply": [_VP, _I32, _VP, _VP, _VP, _VP, _VP],
     "rpa_kinetic_precond_destroy": [_VP],
     "rpa_last_cocg_timing": [_VP, _VP, _VP, _VP, _VP, _VP],
+    "rpa_last_iteration_stats": [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP],
+    "rpa_sternheimer_solve": [_VP, _D, _I32, _VP, _VP, ctypes.POINTER(Stats), _VP],
     "rpa_release_workspace": [_VP],
     "rpa_autotune": [_VP, _I32, _I32, ctypes.POINTER(TuneResult), _VP],
     "rpa_server_create": [_VP, _VP],
@@ -172,7 +175,8 @@ class Handle:
 
     def __init__(self, n, L, v_loc, psi, eps, precision="fp64", stern_tol=1e-10,
                  stern_maxit=20000, batch=0, tile_y=0, slots_per_cu=0, inner_tol=0.0,
-                 hbm_budget=0, use_graph=False, proj=None, stream=None):
+                 hbm_budget=0, use_graph=False, proj=None, fp32_maxit=0, lanczos_breakdown=0.0,
+                 stream=None):
         import torch
         self._torch = torch
         dev = torch.device("cuda")
@@ -204,6 +208,8 @@ class Handle:
         prm.slots_per_cu = int(slots_per_cu)
         prm.inner_tol = float(inner_tol)
         prm.use_graph = 1 if use_graph else 0
+        prm.fp32_maxit = int(fp32_maxit)
+        prm.lanczos_breakdown = float(lanczos_breakdown)
         h = ctypes.c_void_p()
         _check(lib().rpa_setup(ctypes.byref(prm), _stream(stream), ctypes.byref(h)), "rpa_setup")
         del keep
@@ -246,6 +252,18 @@ class Handle:
                                 1 if symmetrized else 0, ctypes.byref(st), _stream(stream)),
                "chi0_apply")
         return y, st.as_dict()
+
+    def sternheimer_solve(self, omega, u, stream=None):
+        """Solutions x[v, n] of (H - eps_n - i omega) x = -psi_n * u[v]
+        (complex128 [nvec, n_occ, N])."""
+        u = self._f64(u).reshape(-1, self.N)
+        x = self._torch.empty((u.shape[0], self.n_occ, self.N), dtype=self._torch.complex128,
+                              device="cuda")
+        st = Stats()
+        _check(lib().rpa_sternheimer_solve(self._h, float(omega), u.shape[0], _ptr(u), _ptr(x),
+                                           ctypes.byref(st), _stream(stream)),
+               "rpa_sternheimer_solve")
+        return x, st.as_dict()
 
     def lanczos_energy_density(self, omegas, points, n_lanczos, stream=None):
         om = np.ascontiguousarray(omegas, dtype=np.float64)
@@ -340,6 +358,23 @@ class Handle:
                                                _ptr(xp), _ptr(yp), _stream(stream)),
                "rpa_kinetic_precond_apply", last_error=False)
         return t.complex(yp[:, 0], yp[:, 1])
+
+    def last_iteration_stats(self):
+        """Per-frequency COCG iteration statistics of the last chi0_apply /
+        lanczos_energy_density call: a list of dicts (omega, solves, mean,
+        std, min, max), one per frequency argument of that call."""
+        n = ctypes.c_int32()
+        _check(lib().rpa_last_iteration_stats(self._h, 0, None, None, None, None, None, None,
+                                              ctypes.byref(n)), "rpa_last_iteration_stats")
+        k = n.value
+        om, mean, sd = np.zeros(k), np.zeros(k), np.zeros(k)
+        cnt, mn, mx = (np.zeros(k, dtype=np.int64) for _ in range(3))
+        _check(lib().rpa_last_iteration_stats(self._h, k, om.ctypes.data, cnt.ctypes.data,
+                                              mean.ctypes.data, sd.ctypes.data, mn.ctypes.data,
+                                              mx.ctypes.data, ctypes.byref(n)),
+               "rpa_last_iteration_stats")
+        return [{"omega": float(om[i]), "solves": int(cnt[i]), "mean": float(mean[i]),
+                 "std": float(sd[i]), "min": int(mn[i]), "max": int(mx[i])} for i in range(k)]
 
     def last_cocg_timing(self):
         ms = ctypes.c_double()

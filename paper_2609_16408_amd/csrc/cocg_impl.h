@@ -762,6 +762,20 @@ __device__ __forceinline__ void cdiv(double ar, double ai, double br, double bi,
 }
 
 __device__ __forceinline__ void record(const CocgArgs& a, int s, int its, int cycles, int status) {
+  // per-frequency statistics of finished solves; a solve the FP32 launch hands
+  // over (status 3) is counted once, by the FP64 launch, with the FP32
+  // iterations (still in out_iters) added
+  if (a.ostats != nullptr && status != 3) {
+    unsigned long long tot = (unsigned long long)its;
+    if (a.n_items_dev != nullptr) tot += (unsigned long long)a.out_iters[s];
+    const int nb = a.n_bins;
+    const int bin = a.obin[s / a.n_occ];
+    atomicAdd(&a.ostats[bin], 1ULL);
+    atomicAdd(&a.ostats[nb + bin], tot);
+    atomicAdd(&a.ostats[2 * nb + bin], tot * tot);
+    atomicMin(&a.ostats[3 * nb + bin], tot);
+    atomicMax(&a.ostats[4 * nb + bin], tot);
+  }
   a.out_iters[s] = its;
   a.out_cycles[s] = cycles;
   a.out_status[s] = status;
@@ -912,7 +926,7 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, 
     float2* pold = pa;
     float2* pnew = pb;
     while (rnorm > thr) {
-      if (its >= a.maxit) { status = 1; break; }
+      if (its >= a.maxit32) { status = 1; break; }
       double m2[2];
       // the direct form also serves tiles with two halo slots per thread: there
       // the recurrence form's larger centre pipeline is kept in scratch memory

@@ -34,6 +34,8 @@ struct rpa_ctx {
   int precision;
   double tol;
   int maxit;
+  int maxit32;                       // FP32 iterations before the FP64 hand-over
+  double lz_brk;                     // relative Lanczos breakdown threshold
   int batch;
   uint64_t budget;
   double inner_tol;
@@ -60,7 +62,11 @@ struct rpa_ctx {
   // workspaces
   DevBuf x64, slots, u64, racc, vtmp, tmpA, Q, alpha, beta, mlen, active, order, iters, cycles,
       status, counter, stats, omega_b, pos_b, idx_b, gpart, G, dhat, partials, interp_m, shifts, fail,
-      faillist;
+      faillist, obin, ostats;
+  // per-frequency iteration statistics of the current / last call
+  int stat_bins = 0;                 // 0: not recorded
+  std::vector<double> stat_omega;    // frequency of each bin
+  std::vector<unsigned long long> stat_host;   // 5 planes of stat_bins counters
   int interp_kind = -1, interp_stride = -1;
   int interp_dims[3] = {0, 0, 0};
   size_t allocated = 0;
@@ -217,6 +223,9 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Partial Gram sums per start vector (grid-point chunks of the contraction).
+int gram_chunks(long long N) { return (int)std::min<long long>(64, std::max<long long>(1, N / 2048)); }
+
 rpa_status usable(rpa_ctx* h) {
   if (!h) return set_err(RPA_E_ARG, "null handle");
   if (h->broken) return set_err(RPA_E_STATE, "handle unusable after an earlier HIP error");
@@ -274,8 +283,10 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
   const int nocc = h->nocc;
   const bool refine = h->precision == RPA_FP32_REFINE;
   const int n_items = B * nocc;
-  // Galerkin initial guess (MFMA-free FP64 tiles)
-  int n_chunks = (int)std::min<long long>(64, std::max<long long>(1, N / 2048));
+  // Galerkin initial guess: the Gram contraction C = h^3 Psi^T diag(u) Psi
+  // runs on the FP64 matrix cores (k_gram); the energy denominators
+  // (k_gram_finish) and the expansion x0 = Psi G (k_expand) on vector FP64
+  const int n_chunks = gram_chunks(N);
   ENSURE(h, h->gpart, (size_t)B * n_chunks * nocc * nocc * sizeof(double));
   ENSURE(h, h->G, (size_t)B * nocc * nocc * sizeof(double2));
   ENSURE(h, h->x64, (size_t)n_items * N * sizeof(double2));
@@ -330,12 +341,16 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
   a.stats = P<unsigned long long>(h->stats);
   a.tol = h->tol;
   a.maxit = h->maxit;
+  a.maxit32 = h->maxit32;
   a.inner_tol = h->inner_tol;
   a.max_cycles = 0;
   a.nl = h->nl;
   a.n_items_dev = nullptr;
   a.fail_list = refine ? P<int>(h->faillist) : nullptr;
   a.fail_count = refine ? P<int>(h->counter) + 2 : nullptr;
+  a.n_bins = h->stat_bins;
+  a.obin = h->stat_bins > 0 ? P<int>(h->obin) : nullptr;
+  a.ostats = h->stat_bins > 0 ? P<unsigned long long>(h->ostats) : nullptr;
   const size_t shmem = cocg_shmem_bytes(h->geom, h->block, refine, h->nl.n_proj);
   // FP64 COCG for the systems the FP32 launch handed over (usually none; its
   // workgroups then exit at once), in the same slot memory
@@ -378,13 +393,29 @@ rpa_status cocg_events(rpa_ctx* h, hipEvent_t* e0, hipEvent_t* e1) {
   return RPA_OK;
 }
 
-rpa_status begin_stats(rpa_ctx* h, hipStream_t s) {
+// Zero the call's counters.  omegas: the distinct frequencies of the call,
+// one statistics bin each (empty: no per-frequency statistics); B: start
+// vectors per batch (entries of the bin map).
+rpa_status begin_stats(rpa_ctx* h, hipStream_t s, const std::vector<double>& omegas, int B) {
   ENSURE(h, h->stats, 8 * sizeof(unsigned long long));
   ENSURE(h, h->fail, 4 * sizeof(int));
   // fill kernels rather than memset nodes, so the sequence stays capturable
   HIPCHK(h, launch_fill_d(P<double>(h->stats), 0.0, 8, s));
   HIPCHK(h, launch_fill_i(P<int>(h->fail), 0, 4, s));
   h->n_ev_used = 0;
+  h->stat_bins = (int)omegas.size();
+  h->stat_omega = omegas;
+  h->stat_host.clear();
+  if (h->stat_bins > 0) {
+    // sized for at least 64 bins so that calls with few frequencies reuse it
+    const int nb = std::max(64, h->stat_bins);
+    ENSURE(h, h->ostats, 5 * (size_t)nb * sizeof(unsigned long long));
+    ENSURE(h, h->obin, (size_t)std::max(64, B) * sizeof(int));
+    const int b = h->stat_bins;
+    unsigned long long* o = P<unsigned long long>(h->ostats);
+    HIPCHK(h, launch_fill_i(reinterpret_cast<int*>(o), 0, 2LL * 5 * b, s));
+    HIPCHK(h, launch_fill_i(reinterpret_cast<int*>(o + 3 * b), -1, 2LL * b, s));   // min: all ones
+  }
   return RPA_OK;
 }
 
@@ -394,6 +425,11 @@ rpa_status end_stats(rpa_ctx* h, hipStream_t s, rpa_stats* st, double t0, long l
   int fl[4];
   HIPCHK(h, hipMemcpyAsync(dv, h->stats.p, sizeof(dv), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipMemcpyAsync(fl, h->fail.p, sizeof(fl), hipMemcpyDeviceToHost, s));
+  if (h->stat_bins > 0) {
+    h->stat_host.assign(5 * (size_t)h->stat_bins, 0ULL);
+    HIPCHK(h, hipMemcpyAsync(h->stat_host.data(), h->ostats.p,
+                             h->stat_host.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  }
   HIPCHK(h, hipStreamSynchronize(s));
   double tot = 0.0;
   for (int i = 0; i < h->n_ev_used; ++i) {
@@ -582,6 +618,48 @@ std::string nl_build(const rpa_setup_params* p, long long N, double dV, NlHost& 
 }
 
 }  // namespace
+
+namespace rpa {
+
+int pick_tile_y(int ny, int nz, int requested) {
+  if (requested != 0) return requested;
+  if ((long long)ny * nz <= kMaxBlock) return ny;
+  for (int t = ny; t >= kRadius; --t)
+    if (ny % t == 0 && t * nz <= kMaxBlock) return t;
+  return 0;
+}
+
+uint64_t lanczos_workspace_bytes(const rpa_setup_params& p, int B, int n_lanczos, int num_cu,
+                                 bool query_occupancy) {
+  const uint64_t N = (uint64_t)p.n[0] * p.n[1] * p.n[2];
+  const uint64_t b = (uint64_t)std::max(1, B), m = (uint64_t)std::max(1, n_lanczos);
+  const uint64_t nocc = (uint64_t)std::max(1, p.n_occ);
+  const uint64_t items = b * nocc;
+  const bool refine = p.precision == RPA_FP32_REFINE;
+  // Lanczos basis, start/iteration vectors, recurrence scalars and bookkeeping
+  uint64_t bytes = m * b * N * 8 + b * N * 8 + 2 * b * m * 8 + 2 * b * 4 + 4 * b * 8 + 64 + 16;
+  bytes += 2 * b * N * 8;                                   // nu^1/2 transform buffers
+  bytes += b * (uint64_t)gram_chunks((long long)N) * nocc * nocc * 8 + b * nocc * nocc * 16;
+  bytes += items * N * 16;                                  // Sternheimer solutions (FP64)
+  bytes += items * 4 * (refine ? 5 : 4) + 64 * 4;           // order, counts, status, hand-over list
+  bytes += b * N * 8;                                       // accumulated density response
+  Geom g;
+  g.nx = p.n[0]; g.ny = p.n[1]; g.nz = p.n[2];
+  g.ty = pick_tile_y(p.n[1], p.n[2], p.tile_y);
+  if (g.ty <= 0) g.ty = p.n[1];
+  g.ntiles = p.n[1] / g.ty;
+  g.N = (long long)N;
+  const int block = ((g.ty * g.nz + 63) / 64) * 64;
+  int bpc = p.slots_per_cu > 0 ? p.slots_per_cu : 2;
+  if (p.slots_per_cu <= 0 && query_occupancy)
+    bpc = cocg_blocks_per_cu(g, block, refine, std::max(0, p.n_proj));
+  const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(items, (uint64_t)bpc * num_cu));
+  bytes += grid * (uint64_t)cocg_slot_bytes(g, refine);
+  return bytes;
+}
+
+}  // namespace rpa
+
 extern "C" {
 
 rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
@@ -601,16 +679,12 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   ARG_CHECK(p->batch >= 0, "batch must be >= 0");
   for (int i = 0; i < p->n_occ; ++i) ARG_CHECK(std::isfinite(p->eps[i]), "eps must be finite");
   ARG_CHECK(p->inner_tol >= 0 && p->inner_tol < 1, "inner_tol must be in [0, 1)");
+  ARG_CHECK(p->fp32_maxit >= 0, "fp32_maxit must be >= 0");
+  ARG_CHECK(p->lanczos_breakdown >= 0 && p->lanczos_breakdown < 1,
+            "lanczos_breakdown must be in [0, 1)");
   // tile rows
   const int ny = p->n[1], nz = p->n[2];
-  int ty = p->tile_y;
-  if (ty == 0) {
-    if ((long long)ny * nz <= kMaxBlock) ty = ny;
-    else {
-      for (int t = ny; t >= kRadius; --t)
-        if (ny % t == 0 && t * nz <= kMaxBlock) { ty = t; break; }
-    }
-  }
+  const int ty = pick_tile_y(ny, nz, p->tile_y);
   ARG_CHECK(ty > 0 && ny % ty == 0 && ((ty * nz + 63) / 64) * 64 <= kMaxBlock,
             "no valid tile_y (ty | ny, ty*nz <= 768)");
   ARG_CHECK(ty == ny || ty >= kRadius, "tile_y must be >= 6 unless it covers the plane");
@@ -646,6 +720,8 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   h->precision = p->precision;
   h->tol = p->stern_tol;
   h->maxit = p->stern_maxit;
+  h->maxit32 = p->fp32_maxit > 0 ? p->fp32_maxit : p->stern_maxit;
+  h->lz_brk = p->lanczos_breakdown > 0 ? p->lanczos_breakdown : 1e-13;
   h->batch = p->batch;
   h->budget = p->hbm_budget;
   // reliable-update factor of the FP32 COCG (residual replaced by the FP64
@@ -776,7 +852,8 @@ rpa_status rpa_destroy(rpa_handle h) {
   DevBuf* bufs[] = {&h->x64, &h->slots, &h->u64, &h->racc, &h->vtmp, &h->tmpA, &h->Q, &h->alpha,
                     &h->beta, &h->mlen, &h->active, &h->order, &h->iters, &h->cycles, &h->status,
                     &h->counter, &h->stats, &h->omega_b, &h->pos_b, &h->idx_b, &h->gpart, &h->G,
-                    &h->dhat, &h->partials, &h->interp_m, &h->shifts, &h->fail, &h->faillist};
+                    &h->dhat, &h->partials, &h->interp_m, &h->shifts, &h->fail, &h->faillist,
+                    &h->obin, &h->ostats};
   for (DevBuf* b : bufs) fr(b->p);
   drop_graphs(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -798,7 +875,7 @@ rpa_status rpa_release_workspace(rpa_handle h) {
   DevBuf* bufs[] = {&h->x64, &h->slots, &h->u64, &h->racc, &h->vtmp, &h->tmpA, &h->Q, &h->alpha,
                     &h->beta, &h->mlen, &h->active, &h->order, &h->iters, &h->cycles, &h->status,
                     &h->counter, &h->gpart, &h->G, &h->dhat, &h->partials, &h->shifts, &h->dres,
-                    &h->nlcoef, &h->faillist};
+                    &h->nlcoef, &h->faillist, &h->obin, &h->ostats};
   for (DevBuf* b : bufs) {
     if (b->p) {
       (void)hipFree(b->p);
@@ -861,8 +938,9 @@ rpa_status chi0_apply(rpa_handle h, double omega, int32_t nvec, const double* x,
   const long long N = h->N;
   int B = h->batch > 0 ? h->batch : 64;
   B = std::min(B, (int)nvec);
-  rpa_status r = begin_stats(h, s);
+  rpa_status r = begin_stats(h, s, std::vector<double>(1, omega), B);
   if (r != RPA_OK) return r;
+  HIPCHK(h, launch_fill_i(P<int>(h->obin), 0, B, s));
   ENSURE(h, h->u64, (size_t)B * N * sizeof(double));
   ENSURE(h, h->omega_b, (size_t)B * sizeof(double));
   std::vector<double> om(B, omega);
@@ -886,6 +964,36 @@ rpa_status chi0_apply(rpa_handle h, double omega, int32_t nvec, const double* x,
     } else {
       HIPCHK(h, hipMemcpyAsync(yout, h->racc.p, (size_t)nb * N * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
+  }
+  return end_stats(h, s, st, t0, (long long)nvec * h->nocc, 0);
+}
+
+rpa_status rpa_sternheimer_solve(rpa_handle h, double omega, int32_t nvec, const double* u,
+                                 double* x, rpa_stats* st, void* stream) {
+  rpa_status r0 = usable(h);
+  if (r0 != RPA_OK) return r0;
+  ARG_CHECK(omega > 0 && std::isfinite(omega), "omega must be positive");
+  ARG_CHECK(nvec >= 1 && u && x, "bad arguments");
+  const double t0 = now_s();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const long long N = h->N;
+  const int B = std::min(h->batch > 0 ? h->batch : 64, (int)nvec);
+  rpa_status r = begin_stats(h, s, std::vector<double>(1, omega), B);
+  if (r != RPA_OK) return r;
+  HIPCHK(h, launch_fill_i(P<int>(h->obin), 0, B, s));
+  ENSURE(h, h->u64, (size_t)B * N * sizeof(double));
+  ENSURE(h, h->omega_b, (size_t)B * sizeof(double));
+  std::vector<double> om(B, omega);
+  HIPCHK(h, hipMemcpyAsync(h->omega_b.p, om.data(), B * sizeof(double), hipMemcpyHostToDevice, s));
+  for (int v0 = 0; v0 < nvec; v0 += B) {
+    const int nb = std::min(B, nvec - v0);
+    HIPCHK(h, hipMemcpyAsync(h->u64.p, u + (size_t)v0 * N, (size_t)nb * N * sizeof(double),
+                             hipMemcpyDeviceToDevice, s));
+    std::vector<double> omn(om.begin(), om.begin() + nb);
+    r = sternheimer_batch(h, nb, omn, nullptr, s);
+    if (r != RPA_OK) return r;
+    HIPCHK(h, hipMemcpyAsync(x + (size_t)v0 * h->nocc * N * 2, h->x64.p,
+                             (size_t)nb * h->nocc * N * sizeof(double2), hipMemcpyDeviceToDevice, s));
   }
   return end_stats(h, s, st, t0, (long long)nvec * h->nocc, 0);
 }
@@ -918,7 +1026,7 @@ rpa_status enqueue_batch(rpa_ctx* h, int nb, int m, hipStream_t s, bool timing) 
     if (r != RPA_OK) return r;
     HIPCHK(h, launch_lanczos_step(k, m, nb, N, P<double>(h->Q), P<double>(h->u64),
                                   P<double>(h->alpha), P<double>(h->beta), P<int>(h->mlen),
-                                  P<int>(h->active), 1e-13, s));
+                                  P<int>(h->active), h->lz_brk, s));
   }
   HIPCHK(h, launch_tridiag_quad(nb, m, P<double>(h->alpha), P<double>(h->beta), P<int>(h->mlen),
                                 nullptr, P<double>(h->dres), P<int>(h->fail), s));
@@ -994,7 +1102,7 @@ rpa_status lanczos_energy_density(rpa_handle h, int32_t n_omega, const double* o
   const long long P_total = (long long)n_omega * n_pts;
   int B = h->batch > 0 ? h->batch : 64;
   B = (int)std::min<long long>(B, P_total);
-  rpa_status r = begin_stats(h, s);
+  rpa_status r = begin_stats(h, s, std::vector<double>(omega, omega + n_omega), B);
   if (r != RPA_OK) return r;
   ENSURE(h, h->Q, (size_t)m * B * N * sizeof(double));
   ENSURE(h, h->u64, (size_t)B * N * sizeof(double));
@@ -1008,6 +1116,7 @@ rpa_status lanczos_energy_density(rpa_handle h, int32_t n_omega, const double* o
   ENSURE(h, h->dres, (size_t)B * sizeof(double));
   std::vector<double> om(B);
   std::vector<long long> pos(B), idx(B);
+  std::vector<int> bin(B);
   for (long long i0 = 0; i0 < P_total; i0 += B) {
     const int nb = (int)std::min<long long>(B, P_total - i0);
     // pair i -> point p = i / n_omega, frequency k = i % n_omega (frequencies mixed per batch)
@@ -1017,8 +1126,10 @@ rpa_status lanczos_energy_density(rpa_handle h, int32_t n_omega, const double* o
       om[b] = omega[k];
       pos[b] = (long long)k * n_pts + p;
       idx[b] = point_idx[p];
+      bin[b] = k;
     }
     HIPCHK(h, hipMemcpyAsync(h->omega_b.p, om.data(), nb * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->obin.p, bin.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
     HIPCHK(h, hipMemcpyAsync(h->pos_b.p, pos.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
     HIPCHK(h, hipMemcpyAsync(h->idx_b.p, idx.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
     std::vector<double> omn(om.begin(), om.begin() + nb);
@@ -1150,7 +1261,7 @@ rpa_status rpa_autotune(rpa_handle h, int32_t n_lanczos, int32_t probe_iters,
     h->geom = g0; h->block = blk0; h->slots_per_cu = slots0; h->tol = tol0; h->maxit = maxit0;
   };
   const int Bp = (int)std::min<long long>(64, std::max<long long>(1, (2LL * h->num_cu * 2 + nocc - 1) / nocc));
-  rpa_status r = begin_stats(h, s);
+  rpa_status r = begin_stats(h, s, std::vector<double>(), Bp);
   if (r != RPA_OK) return r;
   ENSURE(h, h->Q, (size_t)Bp * N * sizeof(double));
   ENSURE(h, h->u64, (size_t)Bp * N * sizeof(double));
@@ -1222,6 +1333,28 @@ rpa_status rpa_autotune(rpa_handle h, int32_t n_lanczos, int32_t probe_iters,
   out->slots_per_cu = best_slots;
   out->batch = h->batch;
   out->system_iters_per_s = best;
+  return RPA_OK;
+}
+
+rpa_status rpa_last_iteration_stats(rpa_handle h, int32_t cap, double* omega, int64_t* count,
+                                    double* mean, double* stdev, int64_t* min_iters,
+                                    int64_t* max_iters, int32_t* n_out) {
+  if (!h) return set_err(RPA_E_ARG, "null handle");
+  ARG_CHECK(cap >= 0, "cap must be >= 0");
+  const int nb = h->stat_host.empty() ? 0 : h->stat_bins;
+  if (n_out) *n_out = nb;
+  const unsigned long long* o = h->stat_host.data();
+  for (int i = 0; i < std::min(nb, (int)cap); ++i) {
+    const double c = (double)o[i];
+    const double m = c > 0 ? (double)o[nb + i] / c : 0.0;
+    const double var = c > 0 ? std::max(0.0, (double)o[2 * nb + i] / c - m * m) : 0.0;
+    if (omega) omega[i] = h->stat_omega[i];
+    if (count) count[i] = (int64_t)o[i];
+    if (mean) mean[i] = m;
+    if (stdev) stdev[i] = std::sqrt(var);
+    if (min_iters) min_iters[i] = c > 0 ? (int64_t)o[3 * nb + i] : 0;
+    if (max_iters) max_iters[i] = (int64_t)o[4 * nb + i];
+  }
   return RPA_OK;
 }
 

@@ -5,6 +5,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "rpa.h"
+
 namespace rpa {
 
 constexpr int kRadius = 6;               // 12th-order central differences
@@ -80,10 +82,30 @@ struct CocgArgs {
   unsigned long long* stats;   // [6]: iters total, iters max, cycles, noconv, breakdown, fallbacks
   double tol;
   int maxit;
+  int maxit32;                 // FP32 iterations before a solve is handed to FP64
   double inner_tol;            // FP32 inner relative reduction
   int max_cycles;
   NlArgs nl;
+  // per-frequency iteration statistics (nullable): bin of each start vector,
+  // and five planes of n_bins counters: solves, sum, sum of squares, min, max
+  const int* obin;
+  unsigned long long* ostats;
+  int n_bins;
 };
+
+// Rows of the stencil tile: `requested` if nonzero, else the whole (y, z)
+// plane when it fits one workgroup, else the tallest divisor of ny (>= 6)
+// whose tile fits.  Returns 0 when no requested or automatic choice is valid.
+int pick_tile_y(int ny, int nz, int requested);
+
+// Device bytes lanczos_energy_density allocates for batches of B start
+// vectors and n_lanczos steps on the problem `p` (the workspaces of the
+// Lanczos basis, nu^1/2, the Galerkin guess, the persistent COCG slots and
+// the bookkeeping), using the launch shape the handle would pick.  With
+// query_occupancy the resident workgroups per CU come from the HIP occupancy
+// calculator (needs a device), else two per CU are assumed.
+uint64_t lanczos_workspace_bytes(const rpa_setup_params& p, int B, int n_lanczos, int num_cu,
+                                 bool query_occupancy);
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_cocg(const CocgArgs& a, bool fp32_refine, int grid, int block, size_t shmem,

@@ -51,16 +51,12 @@ struct Job {
   bool done = false;
 };
 
-// Workspace bytes a job needs (B start vectors of N_s systems): Sternheimer
-// solutions, Lanczos basis, start/iteration vectors, COCG workgroup slots.
-uint64_t job_footprint(const CellDef& c, int n_pts, int n_lanczos, int batch) {
-  const uint64_t B = std::min<uint64_t>(batch > 0 ? batch : 64, (uint64_t)n_pts);
-  const uint64_t N = (uint64_t)c.N;
-  const uint64_t x = B * (uint64_t)c.nocc * N * 16;
-  const uint64_t q = (uint64_t)n_lanczos * B * N * 8;
-  const uint64_t vecs = 4 * B * N * 8;
-  const uint64_t slots = 256ULL * 2 * 5 * N * 8;   // up to two workgroups per CU
-  return x + q + vecs + slots + (64ULL << 20);
+// Workspace bytes a job needs: exactly the buffers lanczos_energy_density
+// allocates for a batch of start vectors (the engine computes them from the
+// same launch shape it will use), plus a margin for the HIP runtime.
+uint64_t job_footprint(const CellDef& c, int n_pts, int n_lanczos, int num_cu, int device_ok) {
+  const int B = std::min(c.prm.batch > 0 ? c.prm.batch : 64, n_pts);
+  return rpa::lanczos_workspace_bytes(c.prm, B, n_lanczos, num_cu, device_ok != 0) + (16ULL << 20);
 }
 
 }  // namespace
@@ -80,6 +76,8 @@ struct rpa_server_s {
   bool stop = false;
   std::vector<std::thread> workers;
   std::string err;
+  int num_cu = 256;              // compute units of the device (fake executor: 256)
+  int device_ok = 0;             // a HIP device backs the workers
 };
 
 namespace {
@@ -112,6 +110,9 @@ void worker_main(rpa_server_s* S, int device) {
       --S->idle;
     }
     if (!job) break;
+    // the cell table may grow (rpa_server_add_cell) while this job runs:
+    // take the cell's address while the lock is held
+    const CellDef* cell = S->cells[job->cell].get();
     S->in_use += job->footprint;
     S->high_water = std::max(S->high_water, S->resident + S->in_use);
     job->info.t_start = now_s();
@@ -121,12 +122,12 @@ void worker_main(rpa_server_s* S, int device) {
     rpa_stats js{};
     if (fake) {
       std::this_thread::sleep_for(std::chrono::microseconds(S->prm.fake_executor_us));
-      js.n_systems = (int64_t)job->pts.size() * S->cells[job->cell]->nocc * job->n_lanczos;
+      js.n_systems = (int64_t)job->pts.size() * cell->nocc * job->n_lanczos;
     } else {
       rpa_handle h = nullptr;
       auto it = handles.find(job->cell);
       if (it == handles.end()) {
-        st = rpa_setup(&S->cells[job->cell]->prm, stream, &h);
+        st = rpa_setup(&cell->prm, stream, &h);
         if (st == RPA_OK) handles[job->cell] = h;
       } else {
         h = it->second;
@@ -165,6 +166,13 @@ rpa_status rpa_server_create(const rpa_server_params* p, rpa_server* out) {
     (void)hipGetLastError();
     delete S;
     return RPA_E_HIP;
+  }
+  if (p->fake_executor_us == 0) {
+    S->device_ok = 1;
+    if (hipDeviceGetAttribute(&S->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+      (void)hipGetLastError();
+      S->num_cu = 256;
+    }
   }
   for (int i = 0; i < p->n_workers; ++i) S->workers.emplace_back(worker_main, S, device);
   *out = S;
@@ -252,7 +260,7 @@ rpa_status rpa_server_submit(rpa_server S, int32_t cell_id, double omega, int32_
   j->pts.assign(pts, pts + n_pts);
   j->n_lanczos = n_lanczos;
   j->out = d_out;
-  j->footprint = job_footprint(c, n_pts, n_lanczos, c.prm.batch);
+  j->footprint = job_footprint(c, n_pts, n_lanczos, S->num_cu, S->device_ok);
   if (S->prm.hbm_budget && S->resident + j->footprint > S->prm.hbm_budget) return RPA_E_OOM;
   j->info.t_submit = now_s();
   j->info.footprint = (int64_t)j->footprint;
