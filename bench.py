@@ -41,8 +41,14 @@ WORKLOADS = {
     # largest configuration: 2 points x 8 frequencies = 16 start vectors per step
     # (x alone is 41 GB); every 9th coarse point per axis
     "si216": dict(preset="si216", n_lanczos=8, tol=1e-6, stride=2, interp="tricubic", every=9,
-                  pts_per_step=2, cpu_orbitals=2,
+                  pts_per_step=2,
                   desc="Si216-like 3x3x3 cell, 72^3 grid, 432 orbitals, 864 nonlocal projectors"),
+    # the plain FP64 method on the Si8-like cell at its own settings: N_l = 30,
+    # tol 1e-8, trilinear interpolation, every stride-2 coarse point (54 steps
+    # of 32 points x 8 frequencies cover all 1728)
+    "si8c2": dict(preset="si8", n_lanczos=30, tol=1e-8, stride=2, interp="trilinear", every=1,
+                  pts_per_step=32, precision="fp64",
+                  desc="Si8-like cell, 24^3 grid, 16 orbitals, plain FP64 method (N_l 30, tol 1e-8)"),
 }
 
 
@@ -160,29 +166,109 @@ def stencil_gbps(P, h, cell, torch, nvec=512, reps=5):
     return 16.0 * nvec * N / (t * 1e-3) / 1e9, t
 
 
-def cpu_baseline(cell, cfg, omega, orbitals=8):
-    """Oracle timed on the host: one Lanczos matvec (nu^1/2 chi0 nu^1/2 e_j) for
-    one point at one frequency, restricted to `orbitals` of the occupied
-    orbitals, scaled to points/s of the full method (N_s/orbitals solves per
-    matvec, n_lanczos matvecs per point)."""
+def _cpu_init(root, spec):
     import numpy as np
+    sys.path.insert(0, root)
     from threadpoolctl import threadpool_limits
+    _CPU["lim"] = threadpool_limits(limits=1)
     import oracle as O
-    with threadpool_limits(limits=1):
-        ham = O.Hamiltonian(cell.n, cell.L, cell.v_loc, proj=cell.proj)
-        coul = O.Coulomb(cell.n, cell.L)
-        j = int(cell.N_d // 2)
-        q = np.zeros(cell.N_d)
-        q[j] = 1.0
-        t0 = time.perf_counter()
-        u = coul.half(q)
-        O.chi0_apply(ham, cell.psi[:orbitals], cell.eps[:orbitals], u, omega, tol=cfg["tol"])
-        t = time.perf_counter() - t0
-    per_point = t * (cell.n_occ / orbitals) * cfg["n_lanczos"]
-    return {"value": 1.0 / per_point, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one Lanczos matvec at omega={omega:.4g} for point {j}, {orbitals} of "
-                       f"{cell.n_occ} orbitals, tol {cfg['tol']}, single thread: {t:.2f} s; "
-                       f"scaled x{cell.n_occ // orbitals} orbitals x{cfg['n_lanczos']} Lanczos steps")}
+    _CPU["O"] = O
+    _CPU["psi"] = np.load(spec["psi"], mmap_mode="r")
+    _CPU["eps"] = np.load(spec["eps"])
+    _CPU["ham"] = O.Hamiltonian(spec["n"], spec["L"], np.load(spec["v"]), proj=spec["proj"])
+    _CPU["u"] = np.load(spec["u"])
+
+
+def _cpu_unit(args):
+    """One Sternheimer solve of the oracle (an (omega, orbital) unit of one
+    Lanczos matrix-vector product); returns its seconds and iterations."""
+    omega, n, tol = args
+    st = {}
+    t = time.perf_counter()
+    _CPU["O"].chi0_apply(_CPU["ham"], _CPU["psi"], _CPU["eps"], _CPU["u"], omega, tol=tol,
+                         orbitals=[n], stats=st)
+    return time.perf_counter() - t, st["iters"][0]
+
+
+_CPU = {}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cell, cfg, omegas, workers=None):
+    """The oracle timed on the host, one single-threaded process per core (at
+    most 16): the first Lanczos matrix-vector product of one coarse point
+    (nu^1/2 e_j, then every occupied orbital's Sternheimer solve at the
+    benchmark's tolerance) at all 8 frequencies, (frequency, orbital) units
+    dealt round-robin over the processes.  Those 8 matrix-vector products are
+    the first of the n_lanczos each of the 8 points (j, omega_k) needs; the
+    rate is extrapolated over the remaining Lanczos steps only."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import shutil
+    import tempfile
+    import numpy as np
+    import oracle as O
+    workers = int(workers or min(16, os.cpu_count() or 1))
+    j = int(sc_sublattice_first(cell, cfg))
+    q = np.zeros(cell.N_d)
+    q[j] = 1.0
+    u = O.Coulomb(cell.n, cell.L).half(q)
+    d = tempfile.mkdtemp(prefix="cpu_baseline_")
+    spec = {"n": tuple(cell.n), "L": tuple(cell.L), "proj": cell.proj}
+    for k, arr in (("v", cell.v_loc), ("psi", cell.psi), ("eps", cell.eps), ("u", u)):
+        spec[k] = os.path.join(d, k + ".npy")
+        np.save(spec[k], np.ascontiguousarray(arr, dtype=np.float64))
+    units = [(float(w), n, cfg["tol"]) for n in range(cell.n_occ) for w in omegas]
+    # the longest solves (smallest omega, highest orbitals) first
+    units.sort(key=lambda t: (t[0], -t[1]))
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    try:
+        with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn"),
+                                    initializer=_cpu_init, initargs=(ROOT, spec)) as ex:
+            list(ex.map(abs, range(workers)))          # start every worker before timing
+            t0 = time.perf_counter()
+            res = []
+            for r in ex.map(_cpu_unit, units, chunksize=1):
+                res.append(r)
+                if len(res) % max(1, len(units) // 4) == 0:
+                    log(f"[bench] cpu baseline: {len(res)}/{len(units)} solves after "
+                        f"{time.perf_counter() - t0:.0f}s")
+            wall = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+        shutil.rmtree(d, ignore_errors=True)
+    cpu_s = sum(r[0] for r in res)
+    its = [r[1] for r in res]
+    points = len(omegas)                                  # (j, omega_k) pairs
+    per_point_s = wall * cfg["n_lanczos"] / points
+    return {"value": 1.0 / per_point_s, "unit": "points/s", "cores": workers, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "core_seconds_per_point": cpu_s * cfg["n_lanczos"] / points,
+            "sample": (f"first Lanczos matrix-vector product of coarse point {j} at all {points} "
+                       f"frequencies: {len(units)} Sternheimer solves (all {cell.n_occ} orbitals), "
+                       f"tol {cfg['tol']}, mean {np.mean(its):.1f} COCG iterations, on {workers} "
+                       f"single-threaded processes: {wall:.1f} s wall, {cpu_s:.0f} core-s; "
+                       f"extrapolated x{cfg['n_lanczos']} Lanczos steps")}
+
+
+def sc_sublattice_first(cell, cfg):
+    import synthcell as sc
+    return sc.sublattice_points(cell.n, cfg["stride"], cfg["every"])[0]
 
 
 def serving_run(P, sc, si64_cell, omega, log_fn, n_closed=12, n_open=20, warm=2):
@@ -264,6 +350,8 @@ def main():
     import synthcell as sc
 
     cfg = WORKLOADS[args.workload]
+    if "precision" in cfg:
+        args.precision = cfg["precision"]
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     log(f"[bench] building the {cfg['preset']} cell")
@@ -283,7 +371,7 @@ def main():
 
     def make_handle(precision):
         return P.handle_for_cell(cell, precision=precision, stern_tol=cfg["tol"],
-                                 stern_maxit=20000, batch=64, slots_per_cu=args.slots_per_cu,
+                                 stern_maxit=20000, batch=pps * 8, slots_per_cu=args.slots_per_cu,
                                  tile_y=args.tile_y, inner_tol=args.inner_tol,
                                  use_graph=args.use_graph)
 
@@ -301,7 +389,27 @@ def main():
         d_coarse.index_copy_(1, idx, d)
         e_c, _ = hd.energy_from_coarse(weight, stride, cfg["interp"], d_coarse, want_fine=True)
         tm = hd.last_cocg_timing()
+        st["per_omega"] = hd.last_iteration_stats()
         return st, tm, e_c
+
+    def pool_omega(stats_list):
+        """Per-frequency COCG iteration statistics pooled over steps."""
+        acc = {}
+        for st in stats_list:
+            for r in st["per_omega"]:
+                a = acc.setdefault(r["omega"], [0, 0.0, 0.0, None, 0])
+                a[0] += r["solves"]
+                a[1] += r["mean"] * r["solves"]
+                a[2] += (r["std"] ** 2 + r["mean"] ** 2) * r["solves"]
+                a[3] = r["min"] if a[3] is None else min(a[3], r["min"])
+                a[4] = max(a[4], r["max"])
+        out = []
+        for w in sorted(acc):
+            c, s1, s2, mn, mx = acc[w]
+            m = s1 / c
+            out.append({"omega": w, "solves": c, "mean": round(m, 2),
+                        "std": round(math.sqrt(max(0.0, s2 / c - m * m)), 2), "min": mn, "max": mx})
+        return out
 
     for i in range(args.warmup):
         st, tm, _ = step(h, i)
@@ -333,18 +441,29 @@ def main():
 
     extra = {}
     if not args.no_fp64_compare and args.precision == "fp32_refine":
+        # the plain FP64 GPU form on the same point batches: one untimed
+        # warm-up step, then up to two timed ones
         h64 = make_handle("fp64")
-        i = args.warmup
+        n64 = max(1, min(args.steps, 2))
+        st64, _, _ = step(h64, 0)
+        torch.cuda.synchronize()
         t1 = time.perf_counter()
-        st64, tm64, _ = step(h64, i)
+        sts64, ms64 = [], 0.0
+        for i in range(args.warmup, args.warmup + n64):
+            st, tm, _ = step(h64, i)
+            sts64.append(st)
+            ms64 += tm["ms"]
+            log(f"[bench] fp64 step {i}: {st['seconds']:.2f}s iters/system "
+                f"{st['cocg_iters_total'] / st['n_systems']:.1f} max {st['cocg_iters_max']}")
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t1
-        extra["fp64_points_per_s"] = pps * 8 / t64
+        tot64 = {k: sum(x[k] for x in sts64) for k in ("n_systems", "cocg_iters_total", "refine_cycles")}
+        extra["fp64_points_per_s"] = n64 * pps * 8 / t64
+        extra["fp64_steps"] = n64
         extra["speedup_vs_fp64"] = value / extra["fp64_points_per_s"]
-        extra["fp64_cocg_gbps"] = cocg_algorithmic_bytes(st64, cell.N_d, "fp64", nl_sup) / (tm64["ms"] * 1e-3) / 1e9
+        extra["fp64_cocg_gbps"] = cocg_algorithmic_bytes(tot64, cell.N_d, "fp64", nl_sup) / (ms64 * 1e-3) / 1e9
+        extra["fp64_iters_per_system"] = tot64["cocg_iters_total"] / tot64["n_systems"]
         h64.close()
-        log(f"[bench] fp64 step: {t64:.2f}s iters/system {st64['cocg_iters_total'] / st64['n_systems']:.1f} "
-            f"max {st64['cocg_iters_max']}")
     sgbps, sms = stencil_gbps(P, h, cell, torch)
     extra["stencil_fp32_gbps"] = sgbps
     extra["stencil_fp32_frac"] = sgbps / HBM_PEAK_GBPS
@@ -360,7 +479,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         try:
-            cpu = cpu_baseline(cell, cfg, float(omega[4]), orbitals=cfg.get("cpu_orbitals", 8))
+            log("[bench] cpu baseline (oracle, one process per core)")
+            cpu = cpu_baseline(cell, cfg, [float(w) for w in omega])
+            log(f"[bench] cpu baseline: {cpu['value']:.3g} points/s; {cpu['sample']}")
         except Exception as e:  # the baseline must not hide the GPU result
             log(f"[bench] cpu baseline failed: {e!r}")
 
@@ -391,7 +512,9 @@ def main():
         "launch": {"use_graph": bool(args.use_graph), "autotuned": tuned},
         "cocg": {"iters_per_system": tot["cocg_iters_total"] / max(1, tot["n_systems"]),
                  "refine_cycles_per_system": tot["refine_cycles"] / max(1, tot["n_systems"]),
-                 "noconv": tot["n_noconv"], "E_c_partial": e_c},
+                 "noconv": tot["n_noconv"], "E_c_partial": e_c,
+                 "E_c_complete": bool(needed * pps >= len(subset) and cfg["every"] == 1),
+                 "per_omega": pool_omega(stats)},
     }
     rec.update(extra)
     print(json.dumps(rec), flush=True)
