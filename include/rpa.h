@@ -134,6 +134,23 @@ rpa_status rpa_frequency_rule(int32_t n_omega, double* omega, double* weight);
 rpa_status chi0_apply(rpa_handle h, double omega, int32_t nvec, const double* x, double* y,
                       int32_t symmetrized, rpa_stats* st, void* stream);
 
+/* chi0_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation and result as chi0_apply, but every workspace comes from
+ * one fixed 128 MiB device array that the library holds on each GPU it runs
+ * on until the process ends; the call makes no hipMalloc, hipFree or other
+ * allocating call and records no timing events.  Vectors are processed in
+ * the largest batches (at most the handle's batch) whose workspaces fit the
+ * array.  RPA_E_ARG (nothing launched) when even one vector does not fit:
+ * about 16 B x N_d x n_occ for the solutions plus one COCG workspace per
+ * resident workgroup, so cells up to roughly 24 x 24 x 48 points with 32
+ * orbitals.  All calls on one GPU share the array: calls that overlap in
+ * time on one GPU (other streams, other threads, other handles) race and
+ * must be serialised by the caller.  The array keeps the last call's
+ * contents; everything a call needs zeroed it clears itself. */
+rpa_status chi0_apply_noalloc(rpa_handle h, double omega, int32_t nvec, const double* x, double* y,
+                              int32_t symmetrized, rpa_stats* st, void* stream);
+
 /* Lanczos quadrature (Eqs. 6-7, Algorithm 1): for every pair (k, p)
  * d[k][p] = [f(T_m)]_11, f(x) = log(1-x) + x, T_m from m = n_lanczos steps of
  * Lanczos on nu^1/2 chi0(i omega_k) nu^1/2 started from e_j, j = point_idx[p],

@@ -93,6 +93,7 @@ _SIGS = {
     "rpa_destroy": [_VP],
     "rpa_frequency_rule": [_I32, _VP, _VP],
     "chi0_apply": [_VP, _D, _I32, _VP, _VP, _I32, ctypes.POINTER(Stats), _VP],
+    "chi0_apply_noalloc": [_VP, _D, _I32, _VP, _VP, _I32, ctypes.POINTER(Stats), _VP],
     "lanczos_energy_density": [_VP, _I32, _VP, _I32, _VP, _I32, _VP, ctypes.POINTER(Stats), _VP],
     "interpolate": [_VP, _I32, _I32, _I32, _VP, _VP, _VP],
     "rpa_energy_from_coarse": [_VP, _I32, _VP, _I32, _I32, _VP, _VP, _VP, _VP],
@@ -251,6 +252,18 @@ class Handle:
         _check(lib().chi0_apply(self._h, float(omega), x.shape[0], _ptr(x), _ptr(y),
                                 1 if symmetrized else 0, ctypes.byref(st), _stream(stream)),
                "chi0_apply")
+        return y, st.as_dict()
+
+    def chi0_apply_noalloc(self, omega, x, y=None, symmetrized=False, stream=None):
+        """chi0_apply through the allocation-free entry point; y (FP64
+        [nvec, N] on the device) may be supplied by the caller."""
+        x = self._f64(x).reshape(-1, self.N)
+        if y is None:
+            y = self._torch.empty_like(x)
+        st = Stats()
+        _check(lib().chi0_apply_noalloc(self._h, float(omega), x.shape[0], _ptr(x), _ptr(y),
+                                        1 if symmetrized else 0, ctypes.byref(st), _stream(stream)),
+               "chi0_apply_noalloc")
         return y, st.as_dict()
 
     def sternheimer_solve(self, omega, u, stream=None):

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <type_traits>
@@ -85,6 +86,8 @@ struct rpa_ctx {
   std::vector<int> order_h;
   std::vector<hipEvent_t> evs;   // COCG launch timing events of the current call
   int n_ev_used = 0;
+  void* scratch = nullptr;       // this device's allocation-free workspace array
+  bool no_alloc = false;         // workspaces point into `scratch`: never (re)allocate
   double cocg_ms_total = 0.0;
   int cocg_launches = 0;
 };
@@ -112,6 +115,7 @@ rpa_status set_err(rpa_status s, const std::string& msg) {
 
 rpa_status ensure(rpa_ctx* h, DevBuf& b, size_t bytes) {
   if (b.bytes >= bytes && b.p) return RPA_OK;
+  if (h->no_alloc) return set_err(RPA_E_OOM, "workspace outside the allocation-free scratch layout");
   if (h->capturing) return set_err(RPA_E_STATE, "allocation requested during graph capture");
   ++h->alloc_epoch;
   if (b.p) {
@@ -619,6 +623,42 @@ std::string nl_build(const rpa_setup_params* p, long long N, double dV, NlHost& 
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free chi0 application: one array per GPU (every
+// GPU the library runs on holds it until the process ends).  Host code never
+// passes the array's name to a kernel: it is a host-side stand-in, not a
+// device address.  The device address comes from hipGetSymbolAddress, once
+// per device with that device current, and is used everywhere else.
+constexpr size_t kScratchBytes = 128ull << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (nullptr and an error
+// message when it cannot be had).
+void* scratch_on_current_device(std::string* err) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    *err = "no current HIP device for the scratch array";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+      (void)hipGetLastError();
+      *err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 namespace rpa {
 
 int pick_tile_y(int ny, int nz, int requested) {
@@ -836,6 +876,10 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
     (void)hipGetLastError();
     return fail(RPA_E_HIP);
   }
+  {
+    std::string serr;
+    h->scratch = scratch_on_current_device(&serr);   // nullptr: the allocation-free path reports it
+  }
   *out = h;
   g_err.clear();
   return RPA_OK;
@@ -927,17 +971,15 @@ rpa_status rpa_coulomb_apply(rpa_handle h, int32_t power, int32_t nvec, const do
   return coulomb(h, power, nvec, x, y, reinterpret_cast<hipStream_t>(stream));
 }
 
-rpa_status chi0_apply(rpa_handle h, double omega, int32_t nvec, const double* x, double* y,
-                      int32_t symmetrized, rpa_stats* st, void* stream) {
-  rpa_status u = usable(h);
-  if (u != RPA_OK) return u;
-  ARG_CHECK(omega > 0 && std::isfinite(omega), "omega must be positive");
-  ARG_CHECK(nvec >= 1 && x && y, "bad arguments");
+}  // extern "C"
+namespace {
+
+// chi0 x (or nu^1/2 chi0 nu^1/2 x) in batches of B vectors; `timing`
+// records COCG launch events.
+rpa_status chi0_body(rpa_ctx* h, double omega, int32_t nvec, const double* x, double* y,
+                     int32_t symmetrized, rpa_stats* st, hipStream_t s, int B, bool timing) {
   const double t0 = now_s();
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const long long N = h->N;
-  int B = h->batch > 0 ? h->batch : 64;
-  B = std::min(B, (int)nvec);
   rpa_status r = begin_stats(h, s, std::vector<double>(1, omega), B);
   if (r != RPA_OK) return r;
   HIPCHK(h, launch_fill_i(P<int>(h->obin), 0, B, s));
@@ -955,7 +997,7 @@ rpa_status chi0_apply(rpa_handle h, double omega, int32_t nvec, const double* x,
       HIPCHK(h, hipMemcpyAsync(h->u64.p, xin, (size_t)nb * N * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     std::vector<double> omn(om.begin(), om.begin() + nb);
-    r = sternheimer_batch(h, nb, omn, nullptr, s);
+    r = sternheimer_batch(h, nb, omn, nullptr, s, true, timing);
     if (r != RPA_OK) return r;
     double* yout = y + (size_t)v0 * N;
     if (symmetrized) {
@@ -966,6 +1008,103 @@ rpa_status chi0_apply(rpa_handle h, double omega, int32_t nvec, const double* x,
     }
   }
   return end_stats(h, s, st, t0, (long long)nvec * h->nocc, 0);
+}
+
+// Where every workspace of chi0_body for batches of B vectors lies in the
+// scratch array (offsets, 256-byte aligned) and how many bytes it needs in
+// total; the sizes are those chi0_body and its callees ENSURE.
+struct ScratchLayout {
+  struct Item { DevBuf* buf; size_t bytes; };
+  std::vector<Item> items;
+  size_t total = 0;
+};
+
+ScratchLayout scratch_layout(rpa_ctx* h, int B, bool symmetrized) {
+  ScratchLayout L;
+  const size_t N = (size_t)h->N, b = (size_t)B, nocc = (size_t)h->nocc, items = b * nocc;
+  const bool refine = h->precision == RPA_FP32_REFINE;
+  const int bpc = h->slots_per_cu > 0 ? h->slots_per_cu
+                                      : cocg_blocks_per_cu(h->geom, h->block, refine, h->nl.n_proj);
+  const size_t grid = std::max<size_t>(1, std::min<size_t>(items, (size_t)bpc * h->num_cu));
+  auto add = [&](DevBuf& buf, size_t bytes) {
+    L.items.push_back({&buf, bytes});
+    L.total += (bytes + 255) & ~(size_t)255;
+  };
+  add(h->stats, 8 * sizeof(unsigned long long));
+  add(h->fail, 4 * sizeof(int));
+  add(h->ostats, 5 * 64 * sizeof(unsigned long long));
+  add(h->obin, std::max<size_t>(64, b) * sizeof(int));
+  add(h->u64, b * N * sizeof(double));
+  add(h->omega_b, b * sizeof(double));
+  if (symmetrized) {
+    add(h->tmpA, b * N * sizeof(double));
+    add(h->vtmp, b * N * sizeof(double));
+  }
+  add(h->gpart, b * (size_t)gram_chunks(h->N) * nocc * nocc * sizeof(double));
+  add(h->G, b * nocc * nocc * sizeof(double2));
+  add(h->x64, items * N * sizeof(double2));
+  add(h->order, items * sizeof(int));
+  add(h->iters, items * sizeof(int));
+  add(h->cycles, items * sizeof(int));
+  add(h->status, items * sizeof(int));
+  add(h->counter, 64 * sizeof(int));
+  if (refine) add(h->faillist, items * sizeof(int));
+  add(h->slots, grid * (size_t)cocg_slot_bytes(h->geom, refine));
+  add(h->racc, b * N * sizeof(double));
+  return L;
+}
+
+}  // namespace
+extern "C" {
+
+rpa_status chi0_apply(rpa_handle h, double omega, int32_t nvec, const double* x, double* y,
+                      int32_t symmetrized, rpa_stats* st, void* stream) {
+  rpa_status u = usable(h);
+  if (u != RPA_OK) return u;
+  ARG_CHECK(omega > 0 && std::isfinite(omega), "omega must be positive");
+  ARG_CHECK(nvec >= 1 && x && y, "bad arguments");
+  const int B = std::min(h->batch > 0 ? h->batch : 64, (int)nvec);
+  return chi0_body(h, omega, nvec, x, y, symmetrized, st, reinterpret_cast<hipStream_t>(stream), B,
+                   true);
+}
+
+rpa_status chi0_apply_noalloc(rpa_handle h, double omega, int32_t nvec, const double* x, double* y,
+                              int32_t symmetrized, rpa_stats* st, void* stream) {
+  rpa_status u = usable(h);
+  if (u != RPA_OK) return u;
+  ARG_CHECK(omega > 0 && std::isfinite(omega), "omega must be positive");
+  ARG_CHECK(nvec >= 1 && x && y, "bad arguments");
+  if (!h->scratch) return set_err(RPA_E_HIP, "the scratch array of this device is not available");
+  // the largest batch (at most the handle's) whose workspaces fit the scratch
+  int B = std::min(h->batch > 0 ? h->batch : 64, (int)nvec);
+  while (B > 1 && scratch_layout(h, B, symmetrized != 0).total > kScratchBytes) --B;
+  ScratchLayout L = scratch_layout(h, B, symmetrized != 0);
+  if (L.total > kScratchBytes)
+    return set_err(RPA_E_ARG, "problem too large for chi0_apply_noalloc: one vector needs " +
+                                  std::to_string(L.total) + " bytes of workspace, the scratch array holds " +
+                                  std::to_string(kScratchBytes));
+  // point the handle's workspaces into the scratch for this call, then put
+  // its own buffers back (they are neither used nor freed meanwhile)
+  struct Swap {
+    rpa_ctx* h;
+    std::vector<std::pair<DevBuf*, DevBuf>> saved;
+    ~Swap() {
+      for (auto& sv : saved) *sv.first = sv.second;
+      h->no_alloc = false;
+    }
+  } swap{h, {}};
+  char* base = static_cast<char*>(h->scratch);
+  size_t off = 0;
+  for (const auto& it : L.items) {
+    swap.saved.push_back({it.buf, *it.buf});
+    it.buf->p = base + off;
+    it.buf->bytes = it.bytes;
+    off += (it.bytes + 255) & ~(size_t)255;
+  }
+  h->no_alloc = true;
+  // no timing events: creating them is a driver allocation
+  return chi0_body(h, omega, nvec, x, y, symmetrized, st, reinterpret_cast<hipStream_t>(stream), B,
+                   false);
 }
 
 rpa_status rpa_sternheimer_solve(rpa_handle h, double omega, int32_t nvec, const double* u,
