@@ -330,6 +330,10 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=0.0,
                     help="reliable-update factor of the FP32 COCG (0: library default)")
     ap.add_argument("--orbital-cache", default="", help="npz file to reuse/save the orbitals")
+    ap.add_argument("--precond", action="store_true",
+                    help="preconditioned Sternheimer solves (shifted kinetic operator)")
+    ap.add_argument("--precond-window", type=float, nargs=2, default=None, metavar=("LO", "HI"),
+                    help="precondition only the solves with LO <= omega <= HI (HI 0: no bound)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain copy used to scale HBM counters")
@@ -373,7 +377,8 @@ def main():
         return P.handle_for_cell(cell, precision=precision, stern_tol=cfg["tol"],
                                  stern_maxit=20000, batch=pps * 8, slots_per_cu=args.slots_per_cu,
                                  tile_y=args.tile_y, inner_tol=args.inner_tol,
-                                 use_graph=args.use_graph)
+                                 use_graph=args.use_graph, precond=args.precond,
+                                 precond_window=args.precond_window)
 
     h = make_handle(args.precision)
     tuned = None
@@ -501,7 +506,9 @@ def main():
         "config": {"workload": cfg["desc"], "precision": args.precision,
                    "n_lanczos": cfg["n_lanczos"], "stern_tol": cfg["tol"], "n_omega": 8,
                    "points_per_step": pps * 8, "coarse_stride": stride,
-                   "interp": cfg["interp"], "parallelism": "single GPU"},
+                   "interp": cfg["interp"], "precond": bool(args.precond),
+                   "precond_window": args.precond_window,
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg_bytes / cocg_launches if cocg_launches else None,

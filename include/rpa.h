@@ -95,6 +95,18 @@ typedef struct {
   double lanczos_breakdown;   /* Lanczos breakdown threshold (Algorithm 1 recurrence):
                                  T is truncated at the first beta_k <= lanczos_breakdown *
                                  max_i |alpha_i|, k < N_l; in [0, 1), 0 = 1e-13 */
+  int32_t precond;            /* Sternheimer preconditioner (Conclusions and Future Work:
+                                 preconditioned solves): 0 = none (plain COCG);
+                                 1 = shifted kinetic operator M_n = -1/2 Lap_h + sigma_n,
+                                 sigma_n = max(mean(V_loc) - eps_n, 1/4 Ha) - i omega,
+                                 inverted exactly in the per-axis eigenbasis of the FD
+                                 Laplacian; COCG then runs on z = M^-1 r with
+                                 rho = r^T z and the stopping rule stays on ||b - A x||.
+                                 Needs every n[d] <= 64 (RPA_E_ARG otherwise). */
+  double precond_omega_min;   /* with precond = 1: only solves at frequencies omega with */
+  double precond_omega_max;   /* min <= omega <= max are preconditioned (max = 0: no upper
+                                 bound); the others run plain COCG in the same Lanczos
+                                 step.  Both 0: every solve is preconditioned. */
 } rpa_setup_params;
 
 typedef struct {

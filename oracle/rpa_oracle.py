@@ -42,6 +42,10 @@ is silent or ambiguous the reading taken is stated in the docstring:
      M_n = -1/2 Lap_h + sigma_n, sigma_n = max(mean V_loc - eps_n, 1/4 Ha) - i w,
      inverted exactly in the per-axis eigenbasis of Lap_h; the stopping rule
      R8 is unchanged, so the solution tolerance is that of the plain solve.
+  R19 (block COCG, not in the paper, which uses plain COCG): block
+     conjugate gradient over right-hand sides that share (orbital, frequency),
+     with unconjugated transposes; block size 1 is COCG.  In the oracle only,
+     to measure whether it would cut the solves' cost.
   R18 (Conclusions and Future Work, block Lanczos quadrature): block Gauss
      quadrature from Q_1 = [e_j for a group of points]; block three-term
      recurrence with thin QR, full reorthogonalisation as in R7, breakdown when
@@ -68,7 +72,7 @@ __all__ = [
     "correlation_energy_from_coarse", "energy_density", "interp_metrics",
     "coarse_index_set", "KineticPreconditioner", "kinetic_shift", "cocg_precond",
     "block_lanczos", "block_tridiag", "block_quadrature", "energy_density_block",
-    "galerkin_space",
+    "galerkin_space", "block_cocg",
 ]
 
 
@@ -319,11 +323,14 @@ def chi0_apply(ham: Hamiltonian, psi: np.ndarray, eps: np.ndarray, u: np.ndarray
     return r
 
 
-def nuhalf_chi0_nuhalf(ham, coul, psi, eps, omega, tol=1e-10, maxit=20000, exact=False, stats=None):
-    """Matrix-free A~ = nu^1/2 chi0 nu^1/2 (Trace Approximations, Eq. 8)."""
+def nuhalf_chi0_nuhalf(ham, coul, psi, eps, omega, tol=1e-10, maxit=20000, exact=False, stats=None,
+                       precond=None, v_loc=None):
+    """Matrix-free A~ = nu^1/2 chi0 nu^1/2 (Trace Approximations, Eq. 8);
+    with `precond` (and v_loc) the solves are preconditioned (reading R17)."""
     def apply(q):
         u = coul.half(q)
-        r = chi0_apply(ham, psi, eps, u, omega, tol=tol, maxit=maxit, exact=exact, stats=stats)
+        r = chi0_apply(ham, psi, eps, u, omega, tol=tol, maxit=maxit, exact=exact, stats=stats,
+                       precond=precond, v_loc=v_loc)
         return coul.half(r)
     return apply
 
@@ -497,12 +504,14 @@ def interp_metrics(d_direct: np.ndarray, d_interp: np.ndarray, n_atoms: int = 1)
 
 def energy_density(ham: Hamiltonian, coul: Coulomb, psi, eps, omegas, points, n_lanczos: int,
                    tol: float = 1e-10, maxit: int = 20000, exact: bool = False, stats: dict | None = None,
-                   breakdown_rel: float = 1e-13):
+                   breakdown_rel: float = 1e-13, precond=None, v_loc=None):
     """d[k, p] = [f(T_m)]_11 from q_1 = e_{points[p]} at omega_k (Algorithm 1);
-    breakdown_rel is the truncation threshold of reading R7."""
+    breakdown_rel is the truncation threshold of reading R7; `precond` (with
+    v_loc) preconditions the Sternheimer solves (reading R17)."""
     d = np.zeros((len(omegas), len(points)))
     for k, w in enumerate(omegas):
-        A = nuhalf_chi0_nuhalf(ham, coul, psi, eps, w, tol=tol, maxit=maxit, exact=exact, stats=stats)
+        A = nuhalf_chi0_nuhalf(ham, coul, psi, eps, w, tol=tol, maxit=maxit, exact=exact, stats=stats,
+                               precond=precond, v_loc=v_loc)
         for p, j in enumerate(points):
             q1 = np.zeros(ham.N)
             q1[j] = 1.0
@@ -596,6 +605,48 @@ def cocg_precond(apply_A, apply_Minv, b: np.ndarray, x0: np.ndarray, tol: float,
         p = z + (rho_new / rho) * p
         rho = rho_new
     return x, maxit, "noconv"
+
+
+def block_cocg(apply_A, B: np.ndarray, X0: np.ndarray, tol: float, maxit: int):
+    """Block COCG for s right-hand sides of one complex symmetric A (an
+    extension for comparison, not in the paper; reading R19).
+
+    O'Leary's block conjugate gradient with unconjugated transposes:
+    R = B - A X, P = R; per iteration Q = A P, alpha = (P^T Q)^-1 (R^T R),
+    X += P alpha, R -= Q alpha, beta = (R^T R)^-1 (R'^T R'), P = R' + P beta.
+    Columns are N-vectors; stops when every column meets the stopping rule
+    R8, ||b_j - A x_j|| <= tol ||b_j|| on the recursive residual.  With s = 1
+    every iterate equals that of cocg.  Returns (X, iterations, status).
+    """
+    Bm = np.asarray(B, dtype=np.complex128)
+    bn = np.linalg.norm(Bm, axis=0)
+    X = np.array(X0, dtype=np.complex128)
+    R = Bm - np.stack([apply_A(X[:, j]) for j in range(X.shape[1])], axis=1)
+    if np.all(np.linalg.norm(R, axis=0) <= tol * bn):
+        return X, 0, "ok"
+    P = R.copy()
+    rho = R.T @ R
+    for it in range(1, maxit + 1):
+        Q = np.stack([apply_A(P[:, j]) for j in range(P.shape[1])], axis=1)
+        mu = P.T @ Q
+        try:
+            alpha = np.linalg.solve(mu, rho)
+        except np.linalg.LinAlgError:
+            return X, it, "breakdown"
+        X = X + P @ alpha
+        R = R - Q @ alpha
+        if np.all(np.linalg.norm(R, axis=0) <= tol * bn):
+            return X, it, "ok"
+        rho_new = R.T @ R
+        try:
+            beta = np.linalg.solve(rho, rho_new)
+        except np.linalg.LinAlgError:
+            return X, it, "breakdown"
+        if not np.all(np.isfinite(beta)):
+            return X, it, "breakdown"
+        P = R + P @ beta
+        rho = rho_new
+    return X, maxit, "noconv"
 
 
 def block_lanczos(apply_A, Q1: np.ndarray, m: int, breakdown_rel: float = 1e-13):

@@ -45,7 +45,8 @@ class SetupParams(ctypes.Structure):
         ("hbm_budget", ctypes.c_uint64), ("tile_y", ctypes.c_int32),
         ("slots_per_cu", ctypes.c_int32), ("inner_tol", ctypes.c_double),
         ("use_graph", ctypes.c_int32), ("fp32_maxit", ctypes.c_int32),
-        ("lanczos_breakdown", ctypes.c_double),
+        ("lanczos_breakdown", ctypes.c_double), ("precond", ctypes.c_int32),
+        ("precond_omega_min", ctypes.c_double), ("precond_omega_max", ctypes.c_double),
     ]
 
 
@@ -177,7 +178,7 @@ class Handle:
     def __init__(self, n, L, v_loc, psi, eps, precision="fp64", stern_tol=1e-10,
                  stern_maxit=20000, batch=0, tile_y=0, slots_per_cu=0, inner_tol=0.0,
                  hbm_budget=0, use_graph=False, proj=None, fp32_maxit=0, lanczos_breakdown=0.0,
-                 stream=None):
+                 precond=False, precond_window=None, stream=None):
         import torch
         self._torch = torch
         dev = torch.device("cuda")
@@ -211,6 +212,9 @@ class Handle:
         prm.use_graph = 1 if use_graph else 0
         prm.fp32_maxit = int(fp32_maxit)
         prm.lanczos_breakdown = float(lanczos_breakdown)
+        prm.precond = 1 if precond else 0
+        if precond_window is not None:
+            prm.precond_omega_min, prm.precond_omega_max = (float(v) for v in precond_window)
         h = ctypes.c_void_p()
         _check(lib().rpa_setup(ctypes.byref(prm), _stream(stream), ctypes.byref(h)), "rpa_setup")
         del keep

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_NAME = "librpa_mi355x.so"
 LIB_PATH = os.path.join(PKG, LIB_NAME)
-SOURCES = ["engine.hip", "cocg.hip", "cocg_nl.hip", "kernels.hip", "server.hip", "precond.hip"]
+SOURCES = ["engine.hip", "cocg.hip", "cocg_nl.hip", "cocg_pc.hip", "kernels.hip", "server.hip",
+           "precond.hip"]
 ARCH = "gfx950"
 
 

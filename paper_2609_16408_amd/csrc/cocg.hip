@@ -67,15 +67,22 @@ int cocg_blocks_per_cu(const Geom& g, int block, bool fp32_refine, int n_proj) {
   const size_t shmem = cocg_shmem_bytes(g, block, fp32_refine, n_proj);
   const int m = tile_mode(g, block);
   int nb = 0;
-  const void* fn = n_proj > 0 ? cocg_nl_fn(fp32_refine, m, pitch_for(g))
-                              : cocg_fn_t<false>(fp32_refine, m, pitch_for(g));
+  const void* fn = n_proj > 0 ? cocg_nl_fn(fp32_refine, m, pitch_for(g), g.prec != 0)
+                   : g.prec   ? cocg_pc_fn(fp32_refine, m, pitch_for(g))
+                              : cocg_fn_t<0>(fp32_refine, m, pitch_for(g));
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, shmem);
   if (e != hipSuccess || nb < 1) return 1;
   return nb;
 }
 
+int cocg_prec_regs(const Geom& g, int block) { return prec_regs(g, block); }
+int cocg_prec_regs_max() { return kPrecRegs; }
+
 long long cocg_slot_bytes(const Geom& g, bool fp32_refine) {
-  return fp32_refine ? 5LL * g.N * (long long)sizeof(float2) : 4LL * g.N * (long long)sizeof(double2);
+  // r, q, p_old, p_new (+ the FP32 correction d); preconditioned: + z and a transform buffer
+  const long long extra = g.prec ? 2 : 0;
+  return fp32_refine ? (5LL + extra) * g.N * (long long)sizeof(float2)
+                     : (4LL + extra) * g.N * (long long)sizeof(double2);
 }
 
 namespace {
@@ -107,7 +114,8 @@ hipError_t launch_ht(const Geom& g, const StencilCoef<T>& cf, const T* v, const 
 hipError_t launch_cocg(const CocgArgs& a, bool fp32_refine, int grid, int block, size_t shmem,
                        hipStream_t s) {
   if (a.nl.n_proj > 0) return launch_cocg_nl(a, fp32_refine, grid, block, shmem, s);
-  return launch_cocg_t<false>(a, fp32_refine, grid, block, shmem, s);
+  if (a.prec) return launch_cocg_pc(a, fp32_refine, grid, block, shmem, s);
+  return launch_cocg_t<0>(a, fp32_refine, grid, block, shmem, s);
 }
 
 hipError_t launch_happly(const Geom& g, const StencilCoef<double>& c64, const StencilCoef<float>& c32,

@@ -31,14 +31,23 @@ namespace rpa {
 
 namespace {
 
+template <typename T> struct V2;
+template <> struct V2<float> { typedef float2 t; };
+template <> struct V2<double> { typedef double2 t; };
+
+}  // namespace
+}  // namespace rpa
+
+#include "precond_impl.h"
+
+namespace rpa {
+
+namespace {
+
 constexpr int R = kRadius;
 constexpr int QN = 2 * R + 1;
 constexpr int kMinGap = 4;     // fewest FP32 iterations between reliable updates
 constexpr int kMaxGap = 100;   // most FP32 iterations between true-residual checks
-
-template <typename T> struct V2;
-template <> struct V2<float> { typedef float2 t; };
-template <> struct V2<double> { typedef double2 t; };
 
 __device__ __forceinline__ float2 mk2(float a, float b) { return make_float2(a, b); }
 __device__ __forceinline__ double2 mk2(double a, double b) { return make_double2(a, b); }
@@ -501,7 +510,13 @@ __host__ __device__ inline size_t lds_plane_bytes(const Geom& g, int pitch, bool
   const size_t main = fp32_iter ? 2 * planes_per_step<float>() * rows_pad * pitch * sizeof(float2)
                                 : 2 * planes_per_step<double>() * rows_pad * pitch * sizeof(double2);
   const size_t light = 2 * rows_light * g.nz * sizeof(double2);
-  const size_t b = main > light ? main : light;
+  size_t b = main > light ? main : light;
+  if (g.prec) {
+    // the preconditioner's planes (FP64 for the FP64 solver, which the FP32
+    // path also launches for the systems it hands over)
+    const size_t pb = prec_lds_bytes(g, fp32_iter ? sizeof(float) : sizeof(double));
+    b = b > pb ? b : pb;
+  }
   return (b + 255) & ~(size_t)255;
 }
 
@@ -767,7 +782,7 @@ __device__ __forceinline__ void record(const CocgArgs& a, int s, int its, int cy
   // iterations (still in out_iters) added
   if (a.ostats != nullptr && status != 3) {
     unsigned long long tot = (unsigned long long)its;
-    if (a.n_items_dev != nullptr) tot += (unsigned long long)a.out_iters[s];
+    if (a.is_followup) tot += (unsigned long long)a.out_iters[s];
     const int nb = a.n_bins;
     const int bin = a.obin[s / a.n_occ];
     atomicAdd(&a.ostats[bin], 1ULL);
@@ -789,7 +804,7 @@ __device__ __forceinline__ void record(const CocgArgs& a, int s, int its, int cy
 
 // ---------------------------------------------------------------------------
 // One system, FP64 throughout.
-template <bool FULL, int HS, int PITCH, bool NL>
+template <bool FULL, int HS, int PITCH, bool NL, bool PC>
 __device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red, char* nlc) {
   const Geom& g = a.g;
   const long long N = g.N;
@@ -804,6 +819,11 @@ __device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red, ch
   double2* x = a.x64 + (size_t)s * N;
   const double eps = a.eps[n];
   const double om = a.omega[b];
+  // preconditioned COCG: z = M^-1 r is the stencil operand and rho = r^T z
+  constexpr bool pc = PC;
+  double2* z = pc ? ws + 4 * N : r;
+  double2* tt = ws + 5 * N;
+  const double psr = pc ? fmax(a.prec->vbar - eps, a.prec->floor) : 0.0, psi = -om;
 
   double2* coef = reinterpret_cast<double2*>(nlc);
   NlPoint<double> nlp{a.nl.pm_ptr, a.nl.pm_proj, a.nl.pm_v64, coef};
@@ -830,6 +850,15 @@ __device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red, ch
     zero_sweep(N, x);
   } else {
     const double thr = a.tol * bnorm;
+    if constexpr (PC) {
+      if (rnorm > thr) {
+        double q2[2] = {0.0, 0.0};
+        precond_apply<double>(g, a.prec, r, tt, z, psr, psi, smem, q2[0], q2[1]);
+        block_reduce<2>(q2, red);
+        rho_r = q2[0];
+        rho_i = q2[1];
+      }
+    }
     double br = 0.0, bi = 0.0;
     bool first = true;
     double2* pold = pa;
@@ -837,7 +866,7 @@ __device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red, ch
     while (rnorm > thr) {
       if (its >= a.maxit) { status = 1; break; }
       ApplyPol<double> ap;
-      ap.r = r; ap.pold = pold; ap.pnew = pnew; ap.q = q; ap.v = a.v64;
+      ap.r = z; ap.pold = pold; ap.pnew = pnew; ap.q = q; ap.v = a.v64;
       ap.c0 = a.c64.c0; ap.eps = eps; ap.om = om; ap.br = br; ap.bi = bi; ap.first = first;
       ap.mu_re = ap.mu_im = 0.0;
       march<double, FULL, HS, PITCH>(g, a.c64, ap, lds, 0, g.ntiles);
@@ -853,6 +882,16 @@ __device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red, ch
       block_reduce<3>(u3, red);
       ++its;
       rnorm = sqrt(u3[0]);
+      if constexpr (PC) {
+        if (rnorm > thr) {
+          double q2[2] = {0.0, 0.0};
+          precond_apply<double>(g, a.prec, r, tt, z, psr, psi, smem, q2[0], q2[1]);
+          block_reduce<2>(q2, red);
+          u3[1] = q2[0];
+          u3[2] = q2[1];
+          if (fabs(u3[1]) + fabs(u3[2]) < 1e-300) { status = 2; break; }
+        }
+      }
       cdiv(u3[1], u3[2], rho_r, rho_i, br, bi);
       rho_r = u3[1]; rho_i = u3[2];
       first = false;
@@ -869,7 +908,7 @@ __device__ void solve_fp64(const CocgArgs& a, int s, char* smem, double* red, ch
 // FP32 correction d is folded into the FP64 solution and the residual is
 // replaced by the true FP64 residual b - A x64.  Convergence is declared on
 // the FP64 residual only.
-template <bool FULL, int HS, int PITCH, bool NL>
+template <bool FULL, int HS, int PITCH, bool NL, bool PC>
 __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, char* nlc) {
   const Geom& g = a.g;
   const long long N = g.N;
@@ -884,6 +923,11 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, 
   double2* x = a.x64 + (size_t)s * N;
   const double eps = a.eps[n];
   const double om = a.omega[b];
+  // preconditioned COCG: z = M^-1 r is the stencil operand and rho = r^T z
+  constexpr bool pc = PC;
+  float2* z = pc ? ws + 5 * N : r;
+  float2* tt = ws + 6 * N;
+  const float psr = pc ? (float)fmax(a.prec->vbar - eps, a.prec->floor) : 0.f, psi = (float)(-om);
 
   // nonlocal coefficients: FP64 for the residual sweeps, FP32 for the inner
   // iterations (same LDS region, never live at the same time)
@@ -925,15 +969,25 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, 
     bool exact_q = false;          // q = A p directly (after a residual replacement)
     float2* pold = pa;
     float2* pnew = pb;
+    if constexpr (PC) {
+      if (rnorm > thr) {
+        double q2[2] = {0.0, 0.0};
+        precond_apply<float>(g, a.prec, r, tt, z, psr, psi, smem, q2[0], q2[1]);
+        block_reduce<2>(q2, red);
+        rho_r = q2[0];
+        rho_i = q2[1];
+      }
+    }
     while (rnorm > thr) {
       if (its >= a.maxit32) { status = 1; break; }
       double m2[2];
-      // the direct form also serves tiles with two halo slots per thread: there
-      // the recurrence form's larger centre pipeline is kept in scratch memory
-      if (exact_q || HS == 2) {
+      // the direct form also serves tiles with two halo slots per thread, and
+      // the preconditioned solver: there the recurrence form's larger centre
+      // pipeline is kept in scratch memory
+      if (exact_q || HS == 2 || PC) {
         // bound the drift of the q recurrence: one sweep with p formed on load
         ApplyPol<float> ap;
-        ap.r = r; ap.pold = pold; ap.pnew = pnew; ap.q = q; ap.v = a.v32;
+        ap.r = z; ap.pold = pold; ap.pnew = pnew; ap.q = q; ap.v = a.v32;
         ap.c0 = a.c32.c0; ap.eps = (float)eps; ap.om = (float)om; ap.br = (float)br;
         ap.bi = (float)bi; ap.first = first;
         ap.mu_re = ap.mu_im = 0.0;
@@ -942,7 +996,7 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, 
         exact_q = false;
       } else {
         RecurPol<float> ap;
-        ap.r = r; ap.pold = pold; ap.pnew = pnew; ap.q = q; ap.v = a.v32;
+        ap.r = z; ap.pold = pold; ap.pnew = pnew; ap.q = q; ap.v = a.v32;
         ap.c0 = a.c32.c0; ap.eps = (float)eps; ap.om = (float)om; ap.br = (float)br;
         ap.bi = (float)bi; ap.first = first;
         ap.mu_re = ap.mu_im = 0.0;
@@ -993,6 +1047,17 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, 
         if (rn < 0.5 * best_true) { best_true = rn; no_gain = 0; }
         else if (++no_gain >= 4) { rnorm = rn; status = 1; break; }   // FP32 stagnation
       }
+      if constexpr (PC) {
+        if (rn > thr) {
+          double q2[2] = {0.0, 0.0};
+          precond_apply<float>(g, a.prec, r, tt, z, psr, psi, smem, q2[0], q2[1]);
+          block_reduce<2>(q2, red);
+          rho_nr = q2[0];
+          rho_ni = q2[1];
+          if (!isfinite(rho_nr) || !isfinite(rho_ni)) { failed = true; break; }
+          if (fabs(rho_nr) + fabs(rho_ni) < 1e-300) { status = 2; break; }
+        }
+      }
       cdiv(rho_nr, rho_ni, rho_r, rho_i, br, bi);
       rho_r = rho_nr; rho_i = rho_ni;
       rnorm = rn;
@@ -1017,8 +1082,11 @@ __device__ void solve_refine(const CocgArgs& a, int s, char* smem, double* red, 
 // 2 = y halo with two slots per thread.  PITCH: LDS row pitch (>= nz + 2R).
 // NL: with the nonlocal projector term (a separate kernel, so the
 // projector-free kernels carry none of its code or registers).
-template <bool REFINE, int M, int PITCH, bool NL>
+// V: bit 0 = nonlocal projector term, bit 1 = preconditioned solves.
+template <bool REFINE, int M, int PITCH, int V>
 __global__ void __launch_bounds__(kMaxBlock) k_cocg(CocgArgs a) {
+  constexpr bool NL = (V & 1) != 0;
+  constexpr bool PC = (V & 2) != 0;
   constexpr bool FULL = M == 0;
   constexpr int HS = M == 2 ? 2 : 1;
   extern __shared__ double smem_d[];
@@ -1039,8 +1107,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_cocg(CocgArgs a) {
     const int b = s / a.n_occ;
     const int live = a.active == nullptr ? 1 : uni(a.active[b]);
     if (live) {
-      if (REFINE) solve_refine<FULL, HS, PITCH, NL>(a, s, smem, red, nlc);
-      else solve_fp64<FULL, HS, PITCH, NL>(a, s, smem, red, nlc);
+      if (REFINE) solve_refine<FULL, HS, PITCH, NL, PC>(a, s, smem, red, nlc);
+      else solve_fp64<FULL, HS, PITCH, NL, PC>(a, s, smem, red, nlc);
     } else if (threadIdx.x == 0) {
       a.out_iters[s] = 0;
       a.out_cycles[s] = 0;
@@ -1059,46 +1127,46 @@ int tile_mode(const Geom& g, int block) {
 }
 int pitch_for(const Geom& g) { return g.nz + 2 * R <= 64 ? 64 : 128; }
 
-template <bool REFINE, int M, bool NL>
+template <bool REFINE, int M, int V>
 const void* cocg_fn_p(int pitch) {
-  return pitch == 64 ? reinterpret_cast<const void*>(&k_cocg<REFINE, M, 64, NL>)
-                     : reinterpret_cast<const void*>(&k_cocg<REFINE, M, 128, NL>);
+  return pitch == 64 ? reinterpret_cast<const void*>(&k_cocg<REFINE, M, 64, V>)
+                     : reinterpret_cast<const void*>(&k_cocg<REFINE, M, 128, V>);
 }
-template <bool NL>
+template <int V>
 const void* cocg_fn_t(bool refine, int m, int pitch) {
   if (refine) {
-    if (m == 0) return cocg_fn_p<true, 0, NL>(pitch);
-    if (m == 1) return cocg_fn_p<true, 1, NL>(pitch);
-    return cocg_fn_p<true, 2, NL>(pitch);
+    if (m == 0) return cocg_fn_p<true, 0, V>(pitch);
+    if (m == 1) return cocg_fn_p<true, 1, V>(pitch);
+    return cocg_fn_p<true, 2, V>(pitch);
   }
-  if (m == 0) return cocg_fn_p<false, 0, NL>(pitch);
-  if (m == 1) return cocg_fn_p<false, 1, NL>(pitch);
-  return cocg_fn_p<false, 2, NL>(pitch);
+  if (m == 0) return cocg_fn_p<false, 0, V>(pitch);
+  if (m == 1) return cocg_fn_p<false, 1, V>(pitch);
+  return cocg_fn_p<false, 2, V>(pitch);
 }
 
-template <bool REFINE, int M, int P, bool NL>
+template <bool REFINE, int M, int P, int V>
 hipError_t launch_c(const CocgArgs& a, int grid, int block, size_t shmem, hipStream_t s) {
-  hipLaunchKernelGGL((k_cocg<REFINE, M, P, NL>), dim3(grid), dim3(block), shmem, s, a);
+  hipLaunchKernelGGL((k_cocg<REFINE, M, P, V>), dim3(grid), dim3(block), shmem, s, a);
   return hipGetLastError();
 }
-template <bool REFINE, int M, bool NL>
+template <bool REFINE, int M, int V>
 hipError_t launch_cm(const CocgArgs& a, int pitch, int grid, int block, size_t shmem, hipStream_t s) {
-  return pitch == 64 ? launch_c<REFINE, M, 64, NL>(a, grid, block, shmem, s)
-                     : launch_c<REFINE, M, 128, NL>(a, grid, block, shmem, s);
+  return pitch == 64 ? launch_c<REFINE, M, 64, V>(a, grid, block, shmem, s)
+                     : launch_c<REFINE, M, 128, V>(a, grid, block, shmem, s);
 }
-template <bool NL>
+template <int V>
 hipError_t launch_cocg_t(const CocgArgs& a, bool fp32_refine, int grid, int block, size_t shmem,
                          hipStream_t s) {
   const int m = tile_mode(a.g, block);
   const int pitch = pitch_for(a.g);
   if (fp32_refine) {
-    if (m == 0) return launch_cm<true, 0, NL>(a, pitch, grid, block, shmem, s);
-    if (m == 1) return launch_cm<true, 1, NL>(a, pitch, grid, block, shmem, s);
-    return launch_cm<true, 2, NL>(a, pitch, grid, block, shmem, s);
+    if (m == 0) return launch_cm<true, 0, V>(a, pitch, grid, block, shmem, s);
+    if (m == 1) return launch_cm<true, 1, V>(a, pitch, grid, block, shmem, s);
+    return launch_cm<true, 2, V>(a, pitch, grid, block, shmem, s);
   }
-  if (m == 0) return launch_cm<false, 0, NL>(a, pitch, grid, block, shmem, s);
-  if (m == 1) return launch_cm<false, 1, NL>(a, pitch, grid, block, shmem, s);
-  return launch_cm<false, 2, NL>(a, pitch, grid, block, shmem, s);
+  if (m == 0) return launch_cm<false, 0, V>(a, pitch, grid, block, shmem, s);
+  if (m == 1) return launch_cm<false, 1, V>(a, pitch, grid, block, shmem, s);
+  return launch_cm<false, 2, V>(a, pitch, grid, block, shmem, s);
 }
 
 }  // namespace

@@ -57,6 +57,10 @@ struct rpa_ctx {
   Geom geom;
   int block = 0;
   NlArgs nl{};                       // nonlocal projectors (device layouts)
+  PrecArgs prec{};                   // kinetic preconditioner tables (device addresses)
+  void* prec_mem = nullptr;          // their allocation, ending with a device copy of `prec`
+  const PrecArgs* prec_dev = nullptr;
+  double pc_lo = 0.0, pc_hi = 0.0;   // frequency window of the preconditioned solves (0: open)
   std::vector<void*> nl_mem;         // their allocations
   DevBuf nlcoef;                     // coefficients for the plain operator application
 
@@ -84,6 +88,7 @@ struct rpa_ctx {
   std::vector<std::pair<std::pair<int, int>, GraphEntry>> graphs;
   DevBuf dres;
   std::vector<int> order_h;
+  int counts_h[2] = {0, 0};          // host staging of the two list lengths
   std::vector<hipEvent_t> evs;   // COCG launch timing events of the current call
   int n_ev_used = 0;
   void* scratch = nullptr;       // this device's allocation-free workspace array
@@ -227,6 +232,9 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Grid dimension padded to the 16-wide matrix-core tiles of the preconditioner.
+int prec_pad_host(int n) { return (n + 15) & ~15; }
+
 // Partial Gram sums per start vector (grid-point chunks of the contraction).
 int gram_chunks(long long N) { return (int)std::min<long long>(64, std::max<long long>(1, N / 2048)); }
 
@@ -263,19 +271,43 @@ rpa_status coulomb(rpa_ctx* h, int power, int B, const double* in, double* out, 
 // h->u64), solve all B*nocc systems and accumulate racc[B][N].
 // Processing order of the B*N_s systems: smallest omega first, then the
 // highest orbital (the longest solves start first).  Host-to-device copy.
+// With a preconditioner frequency window the systems are split into two
+// lists, each in that order: order[0, n) those solved without the
+// preconditioner, order[n, 2n) those solved with it; their counts go to
+// counter[4] and counter[5], where the two persistent launches read them.
+bool prec_window(const rpa_ctx* h) { return h->prec_dev && (h->pc_lo > 0.0 || h->pc_hi > 0.0); }
+bool in_window(const rpa_ctx* h, double w) {
+  return w >= h->pc_lo && (h->pc_hi <= 0.0 || w <= h->pc_hi);
+}
+
 rpa_status upload_order_for(rpa_ctx* h, int B, const std::vector<double>& omega_host, hipStream_t s) {
   const int nocc = h->nocc;
   const int n_items = B * nocc;
-  ENSURE(h, h->order, (size_t)n_items * sizeof(int));
-  h->order_h.resize(n_items);
-  std::vector<int>& order = h->order_h;
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+  ENSURE(h, h->order, 2 * (size_t)n_items * sizeof(int));
+  ENSURE(h, h->counter, sizeof(int) * 64);
+  h->order_h.assign(2 * (size_t)n_items, 0);
+  std::vector<int> all(n_items);
+  std::iota(all.begin(), all.end(), 0);
+  std::stable_sort(all.begin(), all.end(), [&](int a, int b) {
     const double wa = omega_host[a / nocc], wb = omega_host[b / nocc];
     if (wa != wb) return wa < wb;
     return (a % nocc) > (b % nocc);
   });
-  HIPCHK(h, hipMemcpyAsync(h->order.p, order.data(), n_items * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!prec_window(h)) {
+    std::copy(all.begin(), all.end(), h->order_h.begin());
+    HIPCHK(h, hipMemcpyAsync(h->order.p, h->order_h.data(), n_items * sizeof(int), hipMemcpyHostToDevice, s));
+    return RPA_OK;
+  }
+  int np = 0, nq = 0;
+  for (int it : all) {
+    if (in_window(h, omega_host[it / nocc])) h->order_h[n_items + nq++] = it;
+    else h->order_h[np++] = it;
+  }
+  h->counts_h[0] = np;
+  h->counts_h[1] = nq;
+  HIPCHK(h, hipMemcpyAsync(h->order.p, h->order_h.data(), 2 * (size_t)n_items * sizeof(int),
+                           hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(P<int>(h->counter) + 4, h->counts_h, 2 * sizeof(int), hipMemcpyHostToDevice, s));
   return RPA_OK;
 }
 
@@ -299,7 +331,7 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
                                P<double>(h->omega_b), P<double2>(h->G), s));
   HIPCHK(h, launch_expand(h->psi64, P<double2>(h->G), B, nocc, N, P<double2>(h->x64), s));
 
-  ENSURE(h, h->order, (size_t)n_items * sizeof(int));
+  ENSURE(h, h->order, 2 * (size_t)n_items * sizeof(int));
   ENSURE(h, h->iters, (size_t)n_items * sizeof(int));
   ENSURE(h, h->cycles, (size_t)n_items * sizeof(int));
   ENSURE(h, h->status, (size_t)n_items * sizeof(int));
@@ -311,7 +343,7 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
   // counter[0]: work queue of the launch; with FP32 refinement counter[1]
   // is the queue of the FP64 launch and counter[2] the number of systems
   // handed to it (listed in faillist)
-  HIPCHK(h, launch_fill_i(P<int>(h->counter), 0, 3, s));
+  HIPCHK(h, launch_fill_i(P<int>(h->counter), 0, 4, s));
   if (refine) ENSURE(h, h->faillist, (size_t)n_items * sizeof(int));
 
   const int bpc = h->slots_per_cu > 0 ? h->slots_per_cu
@@ -355,6 +387,7 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
   a.n_bins = h->stat_bins;
   a.obin = h->stat_bins > 0 ? P<int>(h->obin) : nullptr;
   a.ostats = h->stat_bins > 0 ? P<unsigned long long>(h->ostats) : nullptr;
+  a.prec = h->prec_dev;
   const size_t shmem = cocg_shmem_bytes(h->geom, h->block, refine, h->nl.n_proj);
   // FP64 COCG for the systems the FP32 launch handed over (usually none; its
   // workgroups then exit at once), in the same slot memory
@@ -364,6 +397,7 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
   f.counter = P<int>(h->counter) + 1;
   f.fail_list = nullptr;
   f.fail_count = nullptr;
+  f.is_followup = 1;
   f.slot_bytes = cocg_slot_bytes(h->geom, false);
   const int grid64 = (int)std::max<long long>(1, std::min<long long>(grid, (long long)grid * sb / f.slot_bytes));
   const size_t shmem64 = cocg_shmem_bytes(h->geom, h->block, false, h->nl.n_proj);
@@ -373,7 +407,25 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
     if (es != RPA_OK) return es;
     HIPCHK(h, hipEventRecord(e0, s));
   }
-  HIPCHK(h, launch_cocg(a, refine, grid, h->block, shmem, s));
+  if (prec_window(h)) {
+    // systems outside the frequency window: the plain kernels; inside: the
+    // preconditioned ones (queues counter[0] and counter[3])
+    CocgArgs ap = a;
+    ap.prec = nullptr;
+    ap.g.prec = 0;
+    ap.n_items_dev = P<int>(h->counter) + 4;
+    Geom gp = h->geom;
+    gp.prec = 0;
+    HIPCHK(h, launch_cocg(ap, refine, grid, h->block,
+                          cocg_shmem_bytes(gp, h->block, refine, h->nl.n_proj), s));
+    CocgArgs aq = a;
+    aq.order = P<int>(h->order) + n_items;
+    aq.n_items_dev = P<int>(h->counter) + 5;
+    aq.counter = P<int>(h->counter) + 3;
+    HIPCHK(h, launch_cocg(aq, refine, grid, h->block, shmem, s));
+  } else {
+    HIPCHK(h, launch_cocg(a, refine, grid, h->block, shmem, s));
+  }
   if (refine) HIPCHK(h, launch_cocg(f, false, grid64, h->block, shmem64, s));
   if (timing) HIPCHK(h, hipEventRecord(e1, s));
   h->last_grid = grid;
@@ -681,7 +733,7 @@ uint64_t lanczos_workspace_bytes(const rpa_setup_params& p, int B, int n_lanczos
   bytes += 2 * b * N * 8;                                   // nu^1/2 transform buffers
   bytes += b * (uint64_t)gram_chunks((long long)N) * nocc * nocc * 8 + b * nocc * nocc * 16;
   bytes += items * N * 16;                                  // Sternheimer solutions (FP64)
-  bytes += items * 4 * (refine ? 5 : 4) + 64 * 4;           // order, counts, status, hand-over list
+  bytes += items * 4 * (refine ? 6 : 5) + 64 * 4;           // two order lists, counts, status, hand-over list
   bytes += b * N * 8;                                       // accumulated density response
   Geom g;
   g.nx = p.n[0]; g.ny = p.n[1]; g.nz = p.n[2];
@@ -689,6 +741,7 @@ uint64_t lanczos_workspace_bytes(const rpa_setup_params& p, int B, int n_lanczos
   if (g.ty <= 0) g.ty = p.n[1];
   g.ntiles = p.n[1] / g.ty;
   g.N = (long long)N;
+  g.prec = p.precond != 0;
   const int block = ((g.ty * g.nz + 63) / 64) * 64;
   int bpc = p.slots_per_cu > 0 ? p.slots_per_cu : 2;
   if (p.slots_per_cu <= 0 && query_occupancy)
@@ -722,6 +775,13 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   ARG_CHECK(p->fp32_maxit >= 0, "fp32_maxit must be >= 0");
   ARG_CHECK(p->lanczos_breakdown >= 0 && p->lanczos_breakdown < 1,
             "lanczos_breakdown must be in [0, 1)");
+  ARG_CHECK(p->precond == 0 || p->precond == 1, "precond must be 0 or 1");
+  ARG_CHECK(p->precond_omega_min >= 0 && p->precond_omega_max >= 0 &&
+                (p->precond_omega_max == 0 || p->precond_omega_max >= p->precond_omega_min),
+            "bad preconditioner frequency window");
+  ARG_CHECK(p->precond == 0 || (p->n[0] <= kMaxPrecDim && p->n[1] <= kMaxPrecDim &&
+                                p->n[2] <= kMaxPrecDim),
+            "the Sternheimer preconditioner needs every n[d] <= 64");
   // tile rows
   const int ny = p->n[1], nz = p->n[2];
   const int ty = pick_tile_y(ny, nz, p->tile_y);
@@ -731,8 +791,11 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   {
     Geom gq;
     gq.nx = p->n[0]; gq.ny = ny; gq.nz = nz; gq.ty = ty; gq.ntiles = ny / ty; gq.N = N;
+    gq.prec = p->precond != 0;
     ARG_CHECK(geom_supported(gq), "n[2] must be <= 116");
     const int blk = ((ty * nz + 63) / 64) * 64;
+    ARG_CHECK(!gq.prec || cocg_prec_regs(gq, blk) <= cocg_prec_regs_max(),
+              "the Sternheimer preconditioner needs larger stencil tiles for this grid");
     // FP32 refinement also runs the FP64 kernel (for the systems it hands over)
     ARG_CHECK(p->n_proj < 0 ||
               (cocg_shmem_bytes(gq, blk, p->precision == RPA_FP32_REFINE, p->n_proj) <= 160 * 1024 &&
@@ -761,6 +824,8 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   h->tol = p->stern_tol;
   h->maxit = p->stern_maxit;
   h->maxit32 = p->fp32_maxit > 0 ? p->fp32_maxit : p->stern_maxit;
+  h->pc_lo = p->precond_omega_min;
+  h->pc_hi = p->precond_omega_max;
   h->lz_brk = p->lanczos_breakdown > 0 ? p->lanczos_breakdown : 1e-13;
   h->batch = p->batch;
   h->budget = p->hbm_budget;
@@ -778,6 +843,7 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   h->geom.ty = ty;
   h->geom.ntiles = ny / ty;
   h->geom.N = N;
+  h->geom.prec = p->precond != 0;
   h->block = ((ty * nz + 63) / 64) * 64;
   int dev = 0;
   auto fail = [&](rpa_status st) { rpa_destroy(h); return st; };
@@ -849,6 +915,68 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
 
   std::vector<double> V[3], lam[3];
   for (int d = 0; d < 3; ++d) axis_basis(h->n[d], h->h[d], w, kRadius, V[d], lam[d]);
+  // kinetic preconditioner: per axis the zero-padded basis, its transpose
+  // and -1/2 lambda, in FP32 and FP64, in one allocation
+  std::vector<char> prec_host;
+  size_t prec_off[3][6] = {};
+  if (p->precond) {
+    auto put = [&](size_t bytes) {
+      const size_t o = prec_host.size();
+      prec_host.resize(o + ((bytes + 255) & ~(size_t)255), 0);
+      return o;
+    };
+    for (int d = 0; d < 3; ++d) {
+      const int n = h->n[d], Pd = prec_pad_host(n);
+      const size_t P2 = (size_t)Pd * Pd;
+      prec_off[d][0] = put(P2 * 4); prec_off[d][1] = put(P2 * 4); prec_off[d][2] = put((size_t)Pd * 4);
+      prec_off[d][3] = put(P2 * 8); prec_off[d][4] = put(P2 * 8); prec_off[d][5] = put((size_t)Pd * 8);
+    }
+    const size_t args_off = put(sizeof(PrecArgs));
+    for (int d = 0; d < 3; ++d) {
+      const int n = h->n[d], Pd = prec_pad_host(n);
+      float* v32 = reinterpret_cast<float*>(prec_host.data() + prec_off[d][0]);
+      float* t32 = reinterpret_cast<float*>(prec_host.data() + prec_off[d][1]);
+      float* k32 = reinterpret_cast<float*>(prec_host.data() + prec_off[d][2]);
+      double* v64 = reinterpret_cast<double*>(prec_host.data() + prec_off[d][3]);
+      double* t64 = reinterpret_cast<double*>(prec_host.data() + prec_off[d][4]);
+      double* k64 = reinterpret_cast<double*>(prec_host.data() + prec_off[d][5]);
+      for (int i = 0; i < n; ++i)
+        for (int a = 0; a < n; ++a) {
+          const double x = V[d][(size_t)i * n + a];
+          v64[(size_t)i * Pd + a] = x;
+          t64[(size_t)a * Pd + i] = x;
+          v32[(size_t)i * Pd + a] = (float)x;
+          t32[(size_t)a * Pd + i] = (float)x;
+        }
+      for (int a = 0; a < n; ++a) {
+        k64[a] = -0.5 * lam[d][a];
+        k32[a] = (float)k64[a];
+      }
+    }
+    if (!alloc(&h->prec_mem, prec_host.size())) return fail(RPA_E_OOM);
+    char* base = static_cast<char*>(h->prec_mem);
+    for (int d = 0; d < 3; ++d) {
+      h->prec.v32[d] = reinterpret_cast<const float*>(base + prec_off[d][0]);
+      h->prec.vt32[d] = reinterpret_cast<const float*>(base + prec_off[d][1]);
+      h->prec.k32[d] = reinterpret_cast<const float*>(base + prec_off[d][2]);
+      h->prec.v64[d] = reinterpret_cast<const double*>(base + prec_off[d][3]);
+      h->prec.vt64[d] = reinterpret_cast<const double*>(base + prec_off[d][4]);
+      h->prec.k64[d] = reinterpret_cast<const double*>(base + prec_off[d][5]);
+    }
+    // mean local potential (the real shift of sigma_n)
+    std::vector<double> vh((size_t)N);
+    if (hipMemcpy(vh.data(), p->v_loc, (size_t)N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+      (void)hipGetLastError();
+      g_err = "reading v_loc failed";
+      return fail(RPA_E_HIP);
+    }
+    double sum = 0.0;
+    for (double x : vh) sum += x;
+    h->prec.vbar = sum / (double)N;
+    h->prec.floor = 0.25;
+    memcpy(prec_host.data() + args_off, &h->prec, sizeof(PrecArgs));
+    h->prec_dev = reinterpret_cast<const PrecArgs*>(base + args_off);
+  }
   std::vector<double> sh((size_t)N), sf((size_t)N);
   for (int i = 0; i < h->n[0]; ++i)
     for (int j = 0; j < h->n[1]; ++j)
@@ -869,6 +997,8 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   for (size_t k = 0; k < nl_up.size() && e == hipSuccess; ++k)
     if (nl_up[k].bytes)
       e = hipMemcpyAsync(nl_up[k].dst, nl_up[k].src, nl_up[k].bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && h->prec_mem)
+    e = hipMemcpyAsync(h->prec_mem, prec_host.data(), prec_host.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_d2f(h->v64, h->v32, N, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -891,6 +1021,7 @@ rpa_status rpa_destroy(rpa_handle h) {
   auto fr = [](void* p) { if (p) (void)hipFree(p); };
   fr(h->v64); fr(h->v32); fr(h->psi64); fr(h->eps_d); fr(h->s_half); fr(h->s_full);
   for (void* m : h->nl_mem) fr(m);
+  fr(h->prec_mem);
   fr(h->nlcoef.p);
   for (int d = 0; d < 3; ++d) fr(h->Vax[d]);
   DevBuf* bufs[] = {&h->x64, &h->slots, &h->u64, &h->racc, &h->vtmp, &h->tmpA, &h->Q, &h->alpha,
@@ -1043,7 +1174,7 @@ ScratchLayout scratch_layout(rpa_ctx* h, int B, bool symmetrized) {
   add(h->gpart, b * (size_t)gram_chunks(h->N) * nocc * nocc * sizeof(double));
   add(h->G, b * nocc * nocc * sizeof(double2));
   add(h->x64, items * N * sizeof(double2));
-  add(h->order, items * sizeof(int));
+  add(h->order, 2 * items * sizeof(int));
   add(h->iters, items * sizeof(int));
   add(h->cycles, items * sizeof(int));
   add(h->status, items * sizeof(int));

@@ -31,6 +31,26 @@ struct Geom {
   int ty;          // rows per tile
   int ntiles;      // ny / ty
   long long N;     // nx*ny*nz
+  int prec;        // 1: the COCG solves are preconditioned (workspaces and LDS grow)
+};
+
+constexpr int kMaxPrecDim = 64;          // largest grid dimension of the in-kernel preconditioner
+
+// Shifted kinetic preconditioner M = -1/2 Lap_h + sigma_n, sigma_n =
+// max(vbar - eps_n, floor) - i omega, applied exactly through the per-axis
+// eigenbasis of the periodic FD second derivative.  Per axis d the basis
+// is stored zero-padded to P_d = (n_d rounded up to 16): v[d][i*P_d + a] =
+// mode a at grid point i, vt[d] its transpose, k[d][a] = -1/2 lambda_d(a)
+// (0 beyond n_d); FP32 and FP64 copies.
+struct PrecArgs {
+  const float* v32[3];
+  const float* vt32[3];
+  const float* k32[3];
+  const double* v64[3];
+  const double* vt64[3];
+  const double* k64[3];
+  double vbar;             // mean local potential (Ha)
+  double floor;            // lower bound of the real part of sigma (Ha)
 };
 
 // Separable nonlocal projectors V_nl = h^3 sum_p gamma_p chi_p chi_p^T
@@ -91,6 +111,8 @@ struct CocgArgs {
   const int* obin;
   unsigned long long* ostats;
   int n_bins;
+  const PrecArgs* prec;        // device copy of the preconditioner tables; null: plain COCG
+  int is_followup;             // the FP64 launch that continues systems the FP32 one handed over
 };
 
 // Rows of the stencil tile: `requested` if nonzero, else the whole (y, z)
@@ -113,11 +135,18 @@ hipError_t launch_cocg(const CocgArgs& a, bool fp32_refine, int grid, int block,
 // the kernels with the nonlocal term (separate translation unit)
 hipError_t launch_cocg_nl(const CocgArgs& a, bool fp32_refine, int grid, int block, size_t shmem,
                           hipStream_t s);
-const void* cocg_nl_fn(bool fp32_refine, int tile_mode, int pitch);
+const void* cocg_nl_fn(bool fp32_refine, int tile_mode, int pitch, bool prec);
+// the preconditioned kernels without a nonlocal term (separate translation unit)
+hipError_t launch_cocg_pc(const CocgArgs& a, bool fp32_refine, int grid, int block, size_t shmem,
+                          hipStream_t s);
+const void* cocg_pc_fn(bool fp32_refine, int tile_mode, int pitch);
 size_t cocg_shmem_bytes(const Geom& g, int block, bool fp32_refine, int n_proj);
 int cocg_blocks_per_cu(const Geom& g, int block, bool fp32_refine, int n_proj);
 bool geom_supported(const Geom& g);   // nz + 12 <= 128 (padded LDS rows)
 long long cocg_slot_bytes(const Geom& g, bool fp32_refine);
+// registers per thread the preconditioner's prefetched planes need, and the most it has
+int cocg_prec_regs(const Geom& g, int block);
+int cocg_prec_regs_max();
 
 hipError_t launch_happly(const Geom& g, const StencilCoef<double>& c64, const StencilCoef<float>& c32,
                          const double* v64, const float* v32, int nvec, const double* shift_re,
