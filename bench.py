@@ -32,8 +32,12 @@ CALIB_BYTES = 1 << 30
 
 # workload name -> synthetic cell preset and method settings
 WORKLOADS = {
+    # preconditioned solves for 0.1 <= omega <= 20, where the kinetic
+    # preconditioner's fewer iterations outweigh its per-iteration cost; plain
+    # COCG at the smallest and largest nodes
     "si64": dict(preset="si64", n_lanczos=8, tol=1e-6, stride=2, interp="tricubic", every=3,
-                 pts_per_step=8, desc="Si64-like 2x2x2 cell, 48^3 grid, 128 orbitals"),
+                 pts_per_step=8, precond_window=(0.1, 20.0),
+                 desc="Si64-like 2x2x2 cell, 48^3 grid, 128 orbitals"),
     "si8": dict(preset="si8", n_lanczos=8, tol=1e-6, stride=2, interp="tricubic", every=3,
                 pts_per_step=8, desc="Si8-like cell, 24^3 grid, 16 orbitals"),
     "tiny": dict(preset="tiny", n_lanczos=8, tol=1e-6, stride=2, interp="tricubic", every=1,
@@ -41,7 +45,7 @@ WORKLOADS = {
     # largest configuration: 2 points x 8 frequencies = 16 start vectors per step
     # (x alone is 41 GB); every 9th coarse point per axis
     "si216": dict(preset="si216", n_lanczos=8, tol=1e-6, stride=2, interp="tricubic", every=9,
-                  pts_per_step=2,
+                  pts_per_step=2, progress=True,
                   desc="Si216-like 3x3x3 cell, 72^3 grid, 432 orbitals, 864 nonlocal projectors"),
     # the plain FP64 method on the Si8-like cell at its own settings: N_l = 30,
     # tol 1e-8, trilinear interpolation, every stride-2 coarse point (54 steps
@@ -97,6 +101,35 @@ def cocg_algorithmic_bytes(st: dict, N: int, precision: str, nl_support: int = 0
     return per_pt * N + nl
 
 
+def precond_algorithmic(st: dict, n, precision: str) -> tuple[float, float]:
+    """HBM bytes and MFMA flops of the preconditioner applications on top of
+    cocg_algorithmic_bytes, one application per COCG iteration: three complex
+    passes (yz forward r -> t, x forward/scale/inverse t -> t, yz inverse
+    t -> z), each reading and writing one vector (48 B/pt FP32, 96 B/pt FP64),
+    and a real n_d x n_d basis applied to both parts of the complex vector
+    along each axis, forward and inverse: 8 (n_x + n_y + n_z) flops per point."""
+    N = float(n[0] * n[1] * n[2])
+    its = st["cocg_iters_total"]
+    per_pt = 48.0 if precision == "fp32_refine" else 96.0
+    return per_pt * its * N, 8.0 * float(sum(n)) * its * N
+
+
+def kind_totals(per_omega, precond: bool, window) -> dict:
+    """Per-frequency COCG totals split by the launch that ran them: the plain
+    kernel (kind 0) and the preconditioned one (kind 1), from the pooled
+    per-frequency statistics (a solve handed over to FP64 is counted with its
+    FP32 launch)."""
+    out = {k: {"n_systems": 0, "cocg_iters_total": 0, "refine_cycles": 0} for k in (0, 1)}
+    lo, hi = (window if window is not None else (0.0, 0.0))
+    for r in per_omega:
+        inside = precond and (window is None or (r["omega"] >= lo and (hi <= 0 or r["omega"] <= hi)))
+        o = out[1 if inside else 0]
+        o["n_systems"] += r["solves"]
+        o["cocg_iters_total"] += r["iters_total"]
+        o["refine_cycles"] += r["refine_cycles"]
+    return out
+
+
 def source_sha():
     import hashlib
     h = hashlib.sha256()
@@ -105,10 +138,16 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def pmc_traffic(workload):
-    """HBM bytes per k_cocg launch from the committed rocprofv3 --pmc summary,
-    or None when it is missing, for another workload, or for another version
-    of the kernel source."""
+def cocg_mode(precond: bool, window) -> str:
+    if not precond:
+        return "plain"
+    return "precond" if window is None else f"precond_window {window[0]:g} {window[1]:g}"
+
+
+def pmc_traffic(workload, precond=False, window=None):
+    """HBM bytes per launch of the dominant Sternheimer kernel from the
+    committed rocprofv3 --pmc summary, or None when it is missing, for another
+    workload or solver mode, or for another version of the kernel source."""
     if not os.path.exists(PMC_SUMMARY):
         return None
     vals = {}
@@ -116,7 +155,8 @@ def pmc_traffic(workload):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("workload") != workload or vals.get("cocg_source_sha") != source_sha():
+    if vals.get("workload") != workload or vals.get("cocg_source_sha") != source_sha() or \
+            vals.get("mode", "plain") != cocg_mode(precond, window):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -271,9 +311,11 @@ def sc_sublattice_first(cell, cfg):
     return sc.sublattice_points(cell.n, cfg["stride"], cfg["every"])[0]
 
 
-def serving_run(P, sc, si64_cell, omega, log_fn, n_closed=12, n_open=20, warm=2):
+def serving_run(P, sc, si64_cell, omega, log_fn, n_closed=12, n_open=20, warm=2, n_lanczos=3,
+                tol=0.1, block=256, budget_gb=250.0):
     """Energy-density serving: seeded job mix over resident cells, 3 workers,
-    closed-loop saturation, then Poisson arrivals at 0.5x and 0.9x of it."""
+    closed-loop saturation, then Poisson arrivals at 0.5x and 0.9x of it.
+    The defaults are the light block the default benchmark run includes."""
     import numpy as np
     from paper_2609_16408_amd import serve
     t0 = time.perf_counter()
@@ -281,23 +323,25 @@ def serving_run(P, sc, si64_cell, omega, log_fn, n_closed=12, n_open=20, warm=2)
             sc.preset("si16", seed=411, device="cuda"), sc.preset("si16", seed=412, device="cuda"),
             si64_cell]
     mix = [0.25, 0.25, 0.15, 0.15, 0.20]
-    server = P.Server(n_workers=3, hbm_budget=250 * 10 ** 9)
+    server = P.Server(n_workers=3, hbm_budget=int(budget_gb * 10 ** 9))
     cells = [(server.add_cell(c.n, c.L, c.v_loc, c.psi, c.eps, precision="fp32_refine",
-                              stern_tol=0.1), sc.coarse_points(c.n, 2)) for c in pool]
+                              stern_tol=tol), sc.coarse_points(c.n, 2)) for c in pool]
     log_fn(f"[bench] serving pool ready in {time.perf_counter() - t0:.1f}s")
-    n_lanczos, block = 3, 256
     jobs = serve.make_jobs(n_closed + 2 * n_open, cells, mix, omega, block, seed=4000)
     mem = serve.DeviceMemoryPeak()
-    secs, infos = serve.run_closed(server, cells, jobs[:n_closed], n_lanczos, depth=6, mem=mem)
+    say = lambda m: log_fn("[bench] serving " + m)
+    secs, infos = serve.run_closed(server, cells, jobs[:n_closed], n_lanczos, depth=6, mem=mem,
+                                   log=say)
     sat = len(infos) / secs
-    out = {"workload": "jobs of 256 coarse points at one frequency; 50% Si8-like (24^3, 16 orb), "
+    out = {"workload": f"jobs of {block} coarse points at one frequency; 50% Si8-like (24^3, 16 orb), "
                        "30% Si16-like (24x24x48, 32 orb), 20% Si64-like (48^3, 128 orb); "
-                       "FP32+refine, N_l=3, tol 0.1; 3 workers",
+                       f"FP32+refine, N_l={n_lanczos}, tol {tol:g}; 3 workers",
+           "jobs_closed_loop": n_closed, "jobs_per_load": n_open, "warmup_jobs_excluded": warm,
            "saturation_jobs_per_s": sat}
-    log_fn(f"[bench] serving saturation {sat:.2f} jobs/s")
+    log_fn(f"[bench] serving saturation {sat:.3f} jobs/s")
     for name, frac, lo in (("load_0.5", 0.5, n_closed), ("load_0.9", 0.9, n_closed + n_open)):
         secs, infos = serve.run_open(server, cells, jobs[lo:lo + n_open], n_lanczos,
-                                     rate=frac * sat, seed=4100 + int(10 * frac), mem=mem)
+                                     rate=frac * sat, seed=4100 + int(10 * frac), mem=mem, log=say)
         r = serve.summarize(infos, secs, warm=warm)
         r["points_per_s"] = n_open * block / secs
         out[name] = r
@@ -307,7 +351,7 @@ def serving_run(P, sc, si64_cell, omega, log_fn, n_closed=12, n_open=20, warm=2)
     # device memory actually in use at job completions (whole GPU)
     out["hbm_admitted_high_water_gb"] = st["high_water"] / 1e9
     out["hbm_used_max_gb"] = mem.used_max / 1e9
-    out["hbm_budget_gb"] = 250.0
+    out["hbm_budget_gb"] = budget_gb
     server.close()
     return out
 
@@ -331,10 +375,21 @@ def main():
                     help="reliable-update factor of the FP32 COCG (0: library default)")
     ap.add_argument("--orbital-cache", default="", help="npz file to reuse/save the orbitals")
     ap.add_argument("--precond", action="store_true",
-                    help="preconditioned Sternheimer solves (shifted kinetic operator)")
+                    help="preconditioned Sternheimer solves (shifted kinetic operator) at every "
+                         "frequency")
     ap.add_argument("--precond-window", type=float, nargs=2, default=None, metavar=("LO", "HI"),
                     help="precondition only the solves with LO <= omega <= HI (HI 0: no bound)")
+    ap.add_argument("--plain", action="store_true",
+                    help="plain COCG at every frequency (overrides the workload's default window)")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the serving measurement, at the settings below; prints its own JSON line")
+    ap.add_argument("--serve-nl", type=int, default=8)
+    ap.add_argument("--serve-tol", type=float, default=1e-6)
+    ap.add_argument("--serve-block", type=int, default=32, help="coarse points per job")
+    ap.add_argument("--serve-jobs", type=int, default=110, help="open-loop jobs per load level")
+    ap.add_argument("--serve-closed", type=int, default=24, help="closed-loop jobs (saturation)")
+    ap.add_argument("--serve-budget-gb", type=float, default=288.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain copy used to scale HBM counters")
     args = ap.parse_args()
@@ -356,6 +411,12 @@ def main():
     cfg = WORKLOADS[args.workload]
     if "precision" in cfg:
         args.precision = cfg["precision"]
+    if args.plain:
+        args.precond, args.precond_window = False, None
+    elif args.precond_window is None and not args.precond and "precond_window" in cfg:
+        args.precond_window = list(cfg["precond_window"])
+    if args.precond_window is not None:
+        args.precond = True
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     log(f"[bench] building the {cfg['preset']} cell")
@@ -363,6 +424,14 @@ def main():
     log(f"[bench] cell {cfg['preset']} n={cell.n} N_s={cell.n_occ} gap={cell.gap:.2e} "
         f"eig residual={cell.eig_residual:.1e} setup {time.perf_counter() - t0:.1f}s")
     omega, weight = P.frequency_rule(8)
+    if args.serving_only:
+        # the serving protocol at the given settings (the Si64-like cell of
+        # this workload is the pool's large cell)
+        r = serving_run(P, sc, cell, omega, log, n_closed=args.serve_closed, n_open=args.serve_jobs,
+                        warm=10, n_lanczos=args.serve_nl, tol=args.serve_tol, block=args.serve_block,
+                        budget_gb=args.serve_budget_gb)
+        print(json.dumps({"serving": r, "data": "synthetic", "n_gpus": 1}), flush=True)
+        return
     stride = cfg["stride"]
     coarse = sc.coarse_points(cell.n, stride)
     subset = sc.sublattice_points(cell.n, stride, cfg["every"])
@@ -373,12 +442,13 @@ def main():
     needed = args.warmup + args.steps
     assert needed <= n_batches, "not enough distinct point batches"
 
-    def make_handle(precision):
+    def make_handle(precision, plain=False):
         return P.handle_for_cell(cell, precision=precision, stern_tol=cfg["tol"],
                                  stern_maxit=20000, batch=pps * 8, slots_per_cu=args.slots_per_cu,
                                  tile_y=args.tile_y, inner_tol=args.inner_tol,
-                                 use_graph=args.use_graph, precond=args.precond,
-                                 precond_window=args.precond_window)
+                                 use_graph=args.use_graph, precond=args.precond and not plain,
+                                 precond_window=None if plain else args.precond_window,
+                                 progress=bool(cfg.get("progress", False)))
 
     h = make_handle(args.precision)
     tuned = None
@@ -394,6 +464,7 @@ def main():
         d_coarse.index_copy_(1, idx, d)
         e_c, _ = hd.energy_from_coarse(weight, stride, cfg["interp"], d_coarse, want_fine=True)
         tm = hd.last_cocg_timing()
+        tm["split"] = hd.last_cocg_split()
         st["per_omega"] = hd.last_iteration_stats()
         return st, tm, e_c
 
@@ -402,18 +473,20 @@ def main():
         acc = {}
         for st in stats_list:
             for r in st["per_omega"]:
-                a = acc.setdefault(r["omega"], [0, 0.0, 0.0, None, 0])
+                a = acc.setdefault(r["omega"], [0, 0.0, 0.0, None, 0, 0])
                 a[0] += r["solves"]
                 a[1] += r["mean"] * r["solves"]
                 a[2] += (r["std"] ** 2 + r["mean"] ** 2) * r["solves"]
                 a[3] = r["min"] if a[3] is None else min(a[3], r["min"])
                 a[4] = max(a[4], r["max"])
+                a[5] += r["refine_cycles"]
         out = []
         for w in sorted(acc):
-            c, s1, s2, mn, mx = acc[w]
+            c, s1, s2, mn, mx, cyc = acc[w]
             m = s1 / c
             out.append({"omega": w, "solves": c, "mean": round(m, 2),
-                        "std": round(math.sqrt(max(0.0, s2 / c - m * m)), 2), "min": mn, "max": mx})
+                        "std": round(math.sqrt(max(0.0, s2 / c - m * m)), 2), "min": mn, "max": mx,
+                        "iters_total": int(round(s1)), "refine_cycles": cyc})
         return out
 
     for i in range(args.warmup):
@@ -422,12 +495,15 @@ def main():
             f"{st['cocg_iters_total'] / st['n_systems']:.1f} max {st['cocg_iters_max']}")
     torch.cuda.synchronize()
     stats, cocg_ms, cocg_launches = [], 0.0, 0
+    split_ms = {"plain": 0.0, "precond": 0.0, "followup": 0.0}
     t_start = time.perf_counter()
     for i in range(args.warmup, needed):
         st, tm, e_c = step(h, i)
         stats.append(st)
         cocg_ms += tm["ms"]
         cocg_launches += tm["launches"]
+        for k in split_ms:
+            split_ms[k] += tm["split"][k]
         log(f"[bench] step {i}: {st['seconds']:.2f}s iters/system "
             f"{st['cocg_iters_total'] / st['n_systems']:.1f} max {st['cocg_iters_max']} "
             f"cycles {st['refine_cycles']} noconv {st['n_noconv']}")
@@ -438,17 +514,50 @@ def main():
     tot = {k: sum(s[k] for s in stats) for k in ("n_systems", "cocg_iters_total", "refine_cycles",
                                                  "n_noconv", "n_breakdown")}
     nl_sup = nl_support_points(cell.proj)
-    alg_bytes = cocg_algorithmic_bytes(tot, cell.N_d, args.precision, nl_sup)
-    # graph replay records no per-kernel events: no kernel rate then
-    achieved = alg_bytes / (cocg_ms * 1e-3) / 1e9 if cocg_ms > 0 else None
-    traffic = pmc_traffic(args.workload) if args.precision == "fp32_refine" else None
+    per_omega = pool_omega(stats)
+    kt = kind_totals(per_omega, args.precond, args.precond_window)
     timing = h.last_cocg_timing()
+    # one roofline entry per Sternheimer kernel that ran: algorithmic bytes (and
+    # for the preconditioned kernel also MFMA flops) over that kernel's own
+    # event-timed launches; the FP64 follow-up launch of handed-over solves is
+    # added to the kernel whose solves it finishes
+    kernels = []
+    for kind, name, ms in ((0, "k_cocg (batched Sternheimer COCG)", split_ms["plain"]),
+                           (1, "k_cocg preconditioned (batched Sternheimer PCOCG)", split_ms["precond"])):
+        t = kt[kind]
+        if t["n_systems"] == 0:
+            continue
+        if kind == (1 if args.precond else 0):
+            ms += split_ms["followup"]
+        b = cocg_algorithmic_bytes(t, cell.N_d, args.precision, nl_sup)
+        e = {"kernel": name, "ms": ms, "launches": cocg_launches, "systems": t["n_systems"],
+             "iters_per_system": t["cocg_iters_total"] / t["n_systems"]}
+        if kind == 1:
+            pb, pf = precond_algorithmic(t, cell.n, args.precision)
+            b += pb
+            mfma_peak = 157.3 if args.precision == "fp32_refine" else 78.6
+            e["mfma"] = {"achieved": pf / (ms * 1e-3) / 1e12 if ms > 0 else None, "peak": mfma_peak,
+                         "unit": "TFLOP/s", "flops_per_launch": pf / cocg_launches}
+            e["mfma"]["frac"] = e["mfma"]["achieved"] / mfma_peak if ms > 0 else None
+        e["algorithmic_bytes_per_launch"] = b / cocg_launches
+        # graph replay records no per-kernel events: no kernel rate then
+        e["achieved_gbps"] = b / (ms * 1e-3) / 1e9 if ms > 0 else None
+        e["hbm_frac"] = e["achieved_gbps"] / HBM_PEAK_GBPS if ms > 0 else None
+        kernels.append(e)
+    dom = max(kernels, key=lambda e: e["ms"])
+    alg_bytes = dom["algorithmic_bytes_per_launch"] * cocg_launches
+    achieved = dom["achieved_gbps"]
+    # the preconditioned kernel is priced against whichever ceiling it is closer to
+    use_mfma = "mfma" in dom and dom["mfma"]["frac"] is not None and dom["hbm_frac"] is not None \
+        and dom["mfma"]["frac"] > dom["hbm_frac"]
+    traffic = pmc_traffic(args.workload, args.precond, args.precond_window) \
+        if args.precision == "fp32_refine" else None
 
     extra = {}
     if not args.no_fp64_compare and args.precision == "fp32_refine":
-        # the plain FP64 GPU form on the same point batches: one untimed
-        # warm-up step, then up to two timed ones
-        h64 = make_handle("fp64")
+        # the plain FP64 GPU form (no preconditioner) on the same point
+        # batches: one untimed warm-up step, then up to two timed ones
+        h64 = make_handle("fp64", plain=True)
         n64 = max(1, min(args.steps, 2))
         st64, _, _ = step(h64, 0)
         torch.cuda.synchronize()
@@ -508,12 +617,19 @@ def main():
                    "points_per_step": pps * 8, "coarse_stride": stride,
                    "interp": cfg["interp"], "precond": bool(args.precond),
                    "precond_window": args.precond_window,
+                   "sternheimer_mode": cocg_mode(args.precond, args.precond_window),
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": traffic,
+        "roofline": {"bound": "mfma" if use_mfma else "hbm",
+                     "achieved": dom["mfma"]["achieved"] if use_mfma else achieved,
+                     "peak": dom["mfma"]["peak"] if use_mfma else HBM_PEAK_GBPS,
+                     "unit": "TFLOP/s" if use_mfma else "GB/s",
+                     "frac": dom["mfma"]["frac"] if use_mfma else (achieved / HBM_PEAK_GBPS if achieved else None),
+                     "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg_bytes / cocg_launches if cocg_launches else None,
-                     "kernel": "k_cocg (batched Sternheimer COCG)", "cocg_source_sha": source_sha(),
-                     "launches": cocg_launches, "avg_launch_ms": cocg_ms / max(1, cocg_launches),
+                     "kernel": dom["kernel"], "cocg_source_sha": source_sha(),
+                     "launches": cocg_launches, "avg_launch_ms": dom["ms"] / max(1, cocg_launches),
+                     "all_cocg_avg_launch_ms": cocg_ms / max(1, cocg_launches),
+                     "kernels": kernels,
                      "grid": timing["grid"], "block": timing["block"], "tile_y": timing["tile_y"]},
         "cpu_baseline": cpu,
         "launch": {"use_graph": bool(args.use_graph), "autotuned": tuned},
@@ -521,7 +637,7 @@ def main():
                  "refine_cycles_per_system": tot["refine_cycles"] / max(1, tot["n_systems"]),
                  "noconv": tot["n_noconv"], "E_c_partial": e_c,
                  "E_c_complete": bool(needed * pps >= len(subset) and cfg["every"] == 1),
-                 "per_omega": pool_omega(stats)},
+                 "per_omega": per_omega},
     }
     rec.update(extra)
     print(json.dumps(rec), flush=True)

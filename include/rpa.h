@@ -107,6 +107,10 @@ typedef struct {
   double precond_omega_max;   /* min <= omega <= max are preconditioned (max = 0: no upper
                                  bound); the others run plain COCG in the same Lanczos
                                  step.  Both 0: every solve is preconditioned. */
+  int32_t progress;           /* nonzero: lanczos_energy_density waits for each Lanczos
+                                 step of a batch and prints one line per step to stderr
+                                 (for long runs; eager batches only: a replayed graph
+                                 prints nothing) */
 } rpa_setup_params;
 
 typedef struct {
@@ -257,6 +261,12 @@ rpa_status rpa_kinetic_precond_destroy(rpa_kinetic_precond p);
 rpa_status rpa_last_cocg_timing(rpa_handle h, double* ms, int32_t* launches, int32_t* grid,
                                 int32_t* block, int32_t* tile_y);
 
+/* The Sternheimer launch time of the last call split by kernel (ms, HIP
+ * events): the plain persistent COCG launches (FP32 or FP64), the
+ * preconditioned ones, and the FP64 launches that continue solves the FP32
+ * launch handed over.  Any output may be NULL.  For measurement only. */
+rpa_status rpa_last_cocg_split(rpa_handle h, double* ms_plain, double* ms_prec, double* ms_followup);
+
 /* Per-frequency COCG iteration statistics of the last chi0_apply or
  * lanczos_energy_density call (the quantities of the paper's iteration
  * tables in the Performance section: mean, standard deviation, minimum and
@@ -264,15 +274,16 @@ rpa_status rpa_last_cocg_timing(rpa_handle h, double* ms, int32_t* launches, int
  * per frequency argument of the call (omega[k] of lanczos_energy_density,
  * the single omega of chi0_apply), in that order: omega, the number of
  * solves, and their iteration counts' mean, standard deviation
- * (population), minimum and maximum.  A solve handed from FP32 to FP64 COCG
- * counts once, with the iterations of both.  Outputs are [host] arrays of at
+ * (population), minimum and maximum, and the total of its FP64 reliable
+ * updates (RPA_FP32_REFINE).  A solve handed from FP32 to FP64 COCG counts
+ * once, with the iterations of both.  Outputs are [host] arrays of at
  * least `cap` entries (any may be NULL); n_out receives the number of
  * entries (also when it exceeds cap; then only cap are filled).  The
  * statistics were read back when the call returned: this synchronises
  * nothing. */
 rpa_status rpa_last_iteration_stats(rpa_handle h, int32_t cap, double* omega, int64_t* count,
                                     double* mean, double* stdev, int64_t* min_iters,
-                                    int64_t* max_iters, int32_t* n_out);
+                                    int64_t* max_iters, int64_t* refine_cycles, int32_t* n_out);
 
 /* Launch-shape tuning (the handle's tile rows, workgroups per CU and start
  * vectors per launch).  Each candidate shape -- the whole (y, z) plane if it

@@ -47,6 +47,7 @@ class SetupParams(ctypes.Structure):
         ("use_graph", ctypes.c_int32), ("fp32_maxit", ctypes.c_int32),
         ("lanczos_breakdown", ctypes.c_double), ("precond", ctypes.c_int32),
         ("precond_omega_min", ctypes.c_double), ("precond_omega_max", ctypes.c_double),
+        ("progress", ctypes.c_int32),
     ]
 
 
@@ -106,7 +107,8 @@ _SIGS = {
     "rpa_kinetic_precond_apply": [_VP, _I32, _VP, _VP, _VP, _VP, _VP],
     "rpa_kinetic_precond_destroy": [_VP],
     "rpa_last_cocg_timing": [_VP, _VP, _VP, _VP, _VP, _VP],
-    "rpa_last_iteration_stats": [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP],
+    "rpa_last_cocg_split": [_VP, _VP, _VP, _VP],
+    "rpa_last_iteration_stats": [_VP, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP],
     "rpa_sternheimer_solve": [_VP, _D, _I32, _VP, _VP, ctypes.POINTER(Stats), _VP],
     "rpa_release_workspace": [_VP],
     "rpa_autotune": [_VP, _I32, _I32, ctypes.POINTER(TuneResult), _VP],
@@ -178,7 +180,7 @@ class Handle:
     def __init__(self, n, L, v_loc, psi, eps, precision="fp64", stern_tol=1e-10,
                  stern_maxit=20000, batch=0, tile_y=0, slots_per_cu=0, inner_tol=0.0,
                  hbm_budget=0, use_graph=False, proj=None, fp32_maxit=0, lanczos_breakdown=0.0,
-                 precond=False, precond_window=None, stream=None):
+                 precond=False, precond_window=None, progress=False, stream=None):
         import torch
         self._torch = torch
         dev = torch.device("cuda")
@@ -215,6 +217,7 @@ class Handle:
         prm.precond = 1 if precond else 0
         if precond_window is not None:
             prm.precond_omega_min, prm.precond_omega_max = (float(v) for v in precond_window)
+        prm.progress = 1 if progress else 0
         h = ctypes.c_void_p()
         _check(lib().rpa_setup(ctypes.byref(prm), _stream(stream), ctypes.byref(h)), "rpa_setup")
         del keep
@@ -381,17 +384,25 @@ class Handle:
         lanczos_energy_density call: a list of dicts (omega, solves, mean,
         std, min, max), one per frequency argument of that call."""
         n = ctypes.c_int32()
-        _check(lib().rpa_last_iteration_stats(self._h, 0, None, None, None, None, None, None,
+        _check(lib().rpa_last_iteration_stats(self._h, 0, None, None, None, None, None, None, None,
                                               ctypes.byref(n)), "rpa_last_iteration_stats")
         k = n.value
         om, mean, sd = np.zeros(k), np.zeros(k), np.zeros(k)
-        cnt, mn, mx = (np.zeros(k, dtype=np.int64) for _ in range(3))
+        cnt, mn, mx, cyc = (np.zeros(k, dtype=np.int64) for _ in range(4))
         _check(lib().rpa_last_iteration_stats(self._h, k, om.ctypes.data, cnt.ctypes.data,
                                               mean.ctypes.data, sd.ctypes.data, mn.ctypes.data,
-                                              mx.ctypes.data, ctypes.byref(n)),
+                                              mx.ctypes.data, cyc.ctypes.data, ctypes.byref(n)),
                "rpa_last_iteration_stats")
         return [{"omega": float(om[i]), "solves": int(cnt[i]), "mean": float(mean[i]),
-                 "std": float(sd[i]), "min": int(mn[i]), "max": int(mx[i])} for i in range(k)]
+                 "std": float(sd[i]), "min": int(mn[i]), "max": int(mx[i]),
+                 "refine_cycles": int(cyc[i])} for i in range(k)]
+
+    def last_cocg_split(self):
+        """Sternheimer launch time of the last call (ms) by kernel: plain,
+        preconditioned, FP64 follow-up."""
+        v = [ctypes.c_double() for _ in range(3)]
+        _check(lib().rpa_last_cocg_split(self._h, *(ctypes.byref(x) for x in v)), "rpa_last_cocg_split")
+        return {"plain": v[0].value, "precond": v[1].value, "followup": v[2].value}
 
     def last_cocg_timing(self):
         ms = ctypes.c_double()

@@ -779,10 +779,13 @@ __device__ __forceinline__ void cdiv(double ar, double ai, double br, double bi,
 __device__ __forceinline__ void record(const CocgArgs& a, int s, int its, int cycles, int status) {
   // per-frequency statistics of finished solves; a solve the FP32 launch hands
   // over (status 3) is counted once, by the FP64 launch, with the FP32
-  // iterations (still in out_iters) added
+  // iterations (still in out_iters) added; reliable updates are summed per bin
   if (a.ostats != nullptr && status != 3) {
-    unsigned long long tot = (unsigned long long)its;
-    if (a.is_followup) tot += (unsigned long long)a.out_iters[s];
+    unsigned long long tot = (unsigned long long)its, cyc = (unsigned long long)cycles;
+    if (a.is_followup) {
+      tot += (unsigned long long)a.out_iters[s];
+      cyc += (unsigned long long)a.out_cycles[s];
+    }
     const int nb = a.n_bins;
     const int bin = a.obin[s / a.n_occ];
     atomicAdd(&a.ostats[bin], 1ULL);
@@ -790,6 +793,7 @@ __device__ __forceinline__ void record(const CocgArgs& a, int s, int its, int cy
     atomicAdd(&a.ostats[2 * nb + bin], tot * tot);
     atomicMin(&a.ostats[3 * nb + bin], tot);
     atomicMax(&a.ostats[4 * nb + bin], tot);
+    atomicAdd(&a.ostats[5 * nb + bin], cyc);
   }
   a.out_iters[s] = its;
   a.out_cycles[s] = cycles;

@@ -71,7 +71,7 @@ struct rpa_ctx {
   // per-frequency iteration statistics of the current / last call
   int stat_bins = 0;                 // 0: not recorded
   std::vector<double> stat_omega;    // frequency of each bin
-  std::vector<unsigned long long> stat_host;   // 5 planes of stat_bins counters
+  std::vector<unsigned long long> stat_host;   // 6 planes of stat_bins counters
   int interp_kind = -1, interp_stride = -1;
   int interp_dims[3] = {0, 0, 0};
   size_t allocated = 0;
@@ -81,6 +81,9 @@ struct rpa_ctx {
   int last_grid = 0;
   int use_graph = 0;
   bool capturing = false;
+  int progress = 0;                  // print a line per Lanczos step (waits for it)
+  long long progress_batch = 0;      // batches started in the current call
+  double progress_t0 = 0.0;
   unsigned alloc_epoch = 0;          // bumped whenever a workspace is (re)allocated
   int warm_B = 0, warm_m = 0;        // largest batch run eagerly with the current buffers
   hipStream_t cap_stream = nullptr;  // non-default stream used for capture
@@ -90,7 +93,9 @@ struct rpa_ctx {
   std::vector<int> order_h;
   int counts_h[2] = {0, 0};          // host staging of the two list lengths
   std::vector<hipEvent_t> evs;   // COCG launch timing events of the current call
+  std::vector<int> ev_kind;      // per event pair: 0 plain FP32/FP64, 1 preconditioned, 2 FP64 follow-up
   int n_ev_used = 0;
+  double cocg_ms_kind[3] = {0.0, 0.0, 0.0};
   void* scratch = nullptr;       // this device's allocation-free workspace array
   bool no_alloc = false;         // workspaces point into `scratch`: never (re)allocate
   double cocg_ms_total = 0.0;
@@ -244,7 +249,7 @@ rpa_status usable(rpa_ctx* h) {
   return RPA_OK;
 }
 
-rpa_status cocg_events(rpa_ctx* h, hipEvent_t* e0, hipEvent_t* e1);
+rpa_status cocg_events(rpa_ctx* h, hipEvent_t* e0, hipEvent_t* e1, int kind = 0);
 void drop_graphs(rpa_ctx* h);
 
 // u[B][N] -> out[B][N] = nu^(power/2) u  (Kronecker form; tmp buffers internal)
@@ -401,12 +406,20 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
   f.slot_bytes = cocg_slot_bytes(h->geom, false);
   const int grid64 = (int)std::max<long long>(1, std::min<long long>(grid, (long long)grid * sb / f.slot_bytes));
   const size_t shmem64 = cocg_shmem_bytes(h->geom, h->block, false, h->nl.n_proj);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (timing) {
-    rpa_status es = cocg_events(h, &e0, &e1);
-    if (es != RPA_OK) return es;
-    HIPCHK(h, hipEventRecord(e0, s));
-  }
+  // one pair of timing events around each launch (kind: 0 plain, 1
+  // preconditioned, 2 FP64 follow-up)
+  auto timed = [&](int kind, auto&& launch) -> rpa_status {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timing) {
+      rpa_status es = cocg_events(h, &e0, &e1, kind);
+      if (es != RPA_OK) return es;
+      HIPCHK(h, hipEventRecord(e0, s));
+    }
+    HIPCHK(h, launch());
+    if (timing) HIPCHK(h, hipEventRecord(e1, s));
+    return RPA_OK;
+  };
+  rpa_status rl = RPA_OK;
   if (prec_window(h)) {
     // systems outside the frequency window: the plain kernels; inside: the
     // preconditioned ones (queues counter[0] and counter[3])
@@ -416,18 +429,22 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
     ap.n_items_dev = P<int>(h->counter) + 4;
     Geom gp = h->geom;
     gp.prec = 0;
-    HIPCHK(h, launch_cocg(ap, refine, grid, h->block,
-                          cocg_shmem_bytes(gp, h->block, refine, h->nl.n_proj), s));
+    const size_t shmem_p = cocg_shmem_bytes(gp, h->block, refine, h->nl.n_proj);
+    rl = timed(0, [&] { return launch_cocg(ap, refine, grid, h->block, shmem_p, s); });
+    if (rl != RPA_OK) return rl;
     CocgArgs aq = a;
     aq.order = P<int>(h->order) + n_items;
     aq.n_items_dev = P<int>(h->counter) + 5;
     aq.counter = P<int>(h->counter) + 3;
-    HIPCHK(h, launch_cocg(aq, refine, grid, h->block, shmem, s));
+    rl = timed(1, [&] { return launch_cocg(aq, refine, grid, h->block, shmem, s); });
   } else {
-    HIPCHK(h, launch_cocg(a, refine, grid, h->block, shmem, s));
+    rl = timed(h->prec_dev ? 1 : 0, [&] { return launch_cocg(a, refine, grid, h->block, shmem, s); });
   }
-  if (refine) HIPCHK(h, launch_cocg(f, false, grid64, h->block, shmem64, s));
-  if (timing) HIPCHK(h, hipEventRecord(e1, s));
+  if (rl != RPA_OK) return rl;
+  if (refine) {
+    rl = timed(2, [&] { return launch_cocg(f, false, grid64, h->block, shmem64, s); });
+    if (rl != RPA_OK) return rl;
+  }
   h->last_grid = grid;
 
   ENSURE(h, h->racc, (size_t)B * N * sizeof(double));
@@ -436,13 +453,16 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
   return RPA_OK;
 }
 
-// A pair of timing events for the next COCG launch of this call.
-rpa_status cocg_events(rpa_ctx* h, hipEvent_t* e0, hipEvent_t* e1) {
+// A pair of timing events for the next COCG launch of this call; `kind`
+// tells which launch it times (see rpa_last_cocg_split).
+rpa_status cocg_events(rpa_ctx* h, hipEvent_t* e0, hipEvent_t* e1, int kind) {
   while ((int)h->evs.size() < 2 * (h->n_ev_used + 1)) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) { h->broken = true; return set_err(RPA_E_HIP, "hipEventCreate failed"); }
     h->evs.push_back(e);
   }
+  if ((int)h->ev_kind.size() < h->n_ev_used + 1) h->ev_kind.resize(h->n_ev_used + 1);
+  h->ev_kind[h->n_ev_used] = kind;
   *e0 = h->evs[2 * h->n_ev_used];
   *e1 = h->evs[2 * h->n_ev_used + 1];
   ++h->n_ev_used;
@@ -465,11 +485,11 @@ rpa_status begin_stats(rpa_ctx* h, hipStream_t s, const std::vector<double>& ome
   if (h->stat_bins > 0) {
     // sized for at least 64 bins so that calls with few frequencies reuse it
     const int nb = std::max(64, h->stat_bins);
-    ENSURE(h, h->ostats, 5 * (size_t)nb * sizeof(unsigned long long));
+    ENSURE(h, h->ostats, 6 * (size_t)nb * sizeof(unsigned long long));
     ENSURE(h, h->obin, (size_t)std::max(64, B) * sizeof(int));
     const int b = h->stat_bins;
     unsigned long long* o = P<unsigned long long>(h->ostats);
-    HIPCHK(h, launch_fill_i(reinterpret_cast<int*>(o), 0, 2LL * 5 * b, s));
+    HIPCHK(h, launch_fill_i(reinterpret_cast<int*>(o), 0, 2LL * 6 * b, s));
     HIPCHK(h, launch_fill_i(reinterpret_cast<int*>(o + 3 * b), -1, 2LL * b, s));   // min: all ones
   }
   return RPA_OK;
@@ -482,19 +502,28 @@ rpa_status end_stats(rpa_ctx* h, hipStream_t s, rpa_stats* st, double t0, long l
   HIPCHK(h, hipMemcpyAsync(dv, h->stats.p, sizeof(dv), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipMemcpyAsync(fl, h->fail.p, sizeof(fl), hipMemcpyDeviceToHost, s));
   if (h->stat_bins > 0) {
-    h->stat_host.assign(5 * (size_t)h->stat_bins, 0ULL);
+    h->stat_host.assign(6 * (size_t)h->stat_bins, 0ULL);
     HIPCHK(h, hipMemcpyAsync(h->stat_host.data(), h->ostats.p,
                              h->stat_host.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   }
   HIPCHK(h, hipStreamSynchronize(s));
   double tot = 0.0;
+  for (int k = 0; k < 3; ++k) h->cocg_ms_kind[k] = 0.0;
+  int n_fp32 = 0;
   for (int i = 0; i < h->n_ev_used; ++i) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, h->evs[2 * i], h->evs[2 * i + 1]) == hipSuccess) tot += ms;
-    else (void)hipGetLastError();
+    if (hipEventElapsedTime(&ms, h->evs[2 * i], h->evs[2 * i + 1]) == hipSuccess) {
+      tot += ms;
+      h->cocg_ms_kind[h->ev_kind[i]] += ms;
+    } else {
+      (void)hipGetLastError();
+    }
+    if (h->ev_kind[i] != 2) ++n_fp32;
   }
   h->cocg_ms_total = tot;
-  h->cocg_launches = h->n_ev_used;
+  // launches counted as Sternheimer steps: the FP64 follow-up and, with a
+  // preconditioner window, the second FP32 launch belong to their step
+  h->cocg_launches = prec_window(h) ? n_fp32 / 2 : n_fp32;
   extra_breakdowns += fl[0] + fl[1];
   if (st) {
     st->n_systems = n_systems;
@@ -827,6 +856,7 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   h->pc_lo = p->precond_omega_min;
   h->pc_hi = p->precond_omega_max;
   h->lz_brk = p->lanczos_breakdown > 0 ? p->lanczos_breakdown : 1e-13;
+  h->progress = p->progress;
   h->batch = p->batch;
   h->budget = p->hbm_budget;
   // reliable-update factor of the FP32 COCG (residual replaced by the FP64
@@ -1163,7 +1193,7 @@ ScratchLayout scratch_layout(rpa_ctx* h, int B, bool symmetrized) {
   };
   add(h->stats, 8 * sizeof(unsigned long long));
   add(h->fail, 4 * sizeof(int));
-  add(h->ostats, 5 * 64 * sizeof(unsigned long long));
+  add(h->ostats, 6 * 64 * sizeof(unsigned long long));
   add(h->obin, std::max<size_t>(64, b) * sizeof(int));
   add(h->u64, b * N * sizeof(double));
   add(h->omega_b, b * sizeof(double));
@@ -1297,6 +1327,12 @@ rpa_status enqueue_batch(rpa_ctx* h, int nb, int m, hipStream_t s, bool timing) 
     HIPCHK(h, launch_lanczos_step(k, m, nb, N, P<double>(h->Q), P<double>(h->u64),
                                   P<double>(h->alpha), P<double>(h->beta), P<int>(h->mlen),
                                   P<int>(h->active), h->lz_brk, s));
+    if (h->progress && !h->capturing) {
+      HIPCHK(h, hipStreamSynchronize(s));
+      std::fprintf(stderr, "[rpa] batch %lld (%d start vectors): Lanczos step %d/%d done at %.1f s\n",
+                   h->progress_batch, nb, k + 1, m, now_s() - h->progress_t0);
+      std::fflush(stderr);
+    }
   }
   HIPCHK(h, launch_tridiag_quad(nb, m, P<double>(h->alpha), P<double>(h->beta), P<int>(h->mlen),
                                 nullptr, P<double>(h->dres), P<int>(h->fail), s));
@@ -1387,8 +1423,11 @@ rpa_status lanczos_energy_density(rpa_handle h, int32_t n_omega, const double* o
   std::vector<double> om(B);
   std::vector<long long> pos(B), idx(B);
   std::vector<int> bin(B);
+  h->progress_t0 = t0;
+  h->progress_batch = 0;
   for (long long i0 = 0; i0 < P_total; i0 += B) {
     const int nb = (int)std::min<long long>(B, P_total - i0);
+    ++h->progress_batch;
     // pair i -> point p = i / n_omega, frequency k = i % n_omega (frequencies mixed per batch)
     for (int b = 0; b < nb; ++b) {
       const long long i = i0 + b;
@@ -1608,7 +1647,7 @@ rpa_status rpa_autotune(rpa_handle h, int32_t n_lanczos, int32_t probe_iters,
 
 rpa_status rpa_last_iteration_stats(rpa_handle h, int32_t cap, double* omega, int64_t* count,
                                     double* mean, double* stdev, int64_t* min_iters,
-                                    int64_t* max_iters, int32_t* n_out) {
+                                    int64_t* max_iters, int64_t* refine_cycles, int32_t* n_out) {
   if (!h) return set_err(RPA_E_ARG, "null handle");
   ARG_CHECK(cap >= 0, "cap must be >= 0");
   const int nb = h->stat_host.empty() ? 0 : h->stat_bins;
@@ -1624,7 +1663,16 @@ rpa_status rpa_last_iteration_stats(rpa_handle h, int32_t cap, double* omega, in
     if (stdev) stdev[i] = std::sqrt(var);
     if (min_iters) min_iters[i] = c > 0 ? (int64_t)o[3 * nb + i] : 0;
     if (max_iters) max_iters[i] = (int64_t)o[4 * nb + i];
+    if (refine_cycles) refine_cycles[i] = (int64_t)o[5 * nb + i];
   }
+  return RPA_OK;
+}
+
+rpa_status rpa_last_cocg_split(rpa_handle h, double* ms_plain, double* ms_prec, double* ms_followup) {
+  if (!h) return set_err(RPA_E_ARG, "null handle");
+  if (ms_plain) *ms_plain = h->cocg_ms_kind[0];
+  if (ms_prec) *ms_prec = h->cocg_ms_kind[1];
+  if (ms_followup) *ms_followup = h->cocg_ms_kind[2];
   return RPA_OK;
 }
 

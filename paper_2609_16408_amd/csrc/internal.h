@@ -107,7 +107,8 @@ struct CocgArgs {
   int max_cycles;
   NlArgs nl;
   // per-frequency iteration statistics (nullable): bin of each start vector,
-  // and five planes of n_bins counters: solves, sum, sum of squares, min, max
+  // and six planes of n_bins counters: solves, sum, sum of squares, min, max,
+  // reliable updates
   const int* obin;
   unsigned long long* ostats;
   int n_bins;

@@ -45,8 +45,9 @@ class DeviceMemoryPeak:
             self.used_max = max(self.used_max, total - free)
 
 
-def run_closed(server, cells, jobs, n_lanczos, depth, mem=None):
-    """Keep `depth` jobs in flight; returns (seconds, infos)."""
+def run_closed(server, cells, jobs, n_lanczos, depth, mem=None, log=None, every=10):
+    """Keep `depth` jobs in flight; returns (seconds, infos).  log(msg), if
+    given, is called after every `every` completions."""
     t0 = time.perf_counter()
     inflight, infos, k = [], [], 0
     while k < len(jobs) or inflight:
@@ -58,12 +59,15 @@ def run_closed(server, cells, jobs, n_lanczos, depth, mem=None):
         infos.append(info)
         if mem is not None:
             mem.sample()
+        if log is not None and len(infos) % every == 0:
+            log(f"closed loop: {len(infos)}/{len(jobs)} jobs done at {time.perf_counter() - t0:.1f}s")
     return time.perf_counter() - t0, infos
 
 
-def run_open(server, cells, jobs, n_lanczos, rate, seed, mem=None):
+def run_open(server, cells, jobs, n_lanczos, rate, seed, mem=None, log=None, every=10):
     """Submit at Poisson arrival times of the given rate (jobs/s); returns
-    (seconds, infos) with latency = finish - submit."""
+    (seconds, infos) with latency = finish - submit.  log(msg), if given, is
+    called after every `every` submissions and completions."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, size=len(jobs))
     t0 = time.perf_counter()
@@ -75,11 +79,15 @@ def run_open(server, cells, jobs, n_lanczos, rate, seed, mem=None):
         if dt > 0:
             time.sleep(dt)
         ids.append(server.submit(cells[c][0], w, pts, n_lanczos))
+        if log is not None and len(ids) % every == 0:
+            log(f"open loop: {len(ids)}/{len(jobs)} jobs submitted at {time.perf_counter() - t0:.1f}s")
     infos = []
     for j in ids:
         infos.append(server.wait(j)[1])
         if mem is not None:
             mem.sample()
+        if log is not None and len(infos) % every == 0:
+            log(f"open loop: {len(infos)}/{len(jobs)} jobs done at {time.perf_counter() - t0:.1f}s")
     return time.perf_counter() - t0, infos
 
 

@@ -545,9 +545,10 @@ def si64():
 def test_si64_bench_configuration_fp32_matches_fp64(P, si64):
     """Full Si64-like size in the launch configuration the benchmark times
     (64 start vectors per launch: 8 points x 8 frequencies, N_l = 8, tol 1e-6):
-    every diagonal is <= 0, and the FP32 + refinement energy, extrapolated from
-    these points to the whole stride-2 coarse set, is within 1e-5 Ha/atom of
-    the FP64 path."""
+    every diagonal is <= 0, and the FP32 + refinement energy is within 1e-5
+    Ha/atom of the FP64 path.  The difference is extrapolated as E_c sums the
+    interpolated field: over all N_d fine points (g^3 = 8 per coarse point), so
+    each sampled point stands for N_d / 8 of them."""
     c = si64
     om, w = P.frequency_rule(8)
     pts = sc.sublattice_points(c.n, 2, 3)[:8]
@@ -559,8 +560,7 @@ def test_si64_bench_configuration_fp32_matches_fp64(P, si64):
         h.close()
     d32, d64 = d["fp32_refine"].cpu().numpy(), d["fp64"].cpu().numpy()
     assert (d64 <= 0).all() and (d32 <= 0).all()
-    n_coarse = sc.coarse_points(c.n, 2).size
-    dE = (n_coarse / len(pts)) * float(np.abs(w @ (d32 - d64)).sum()) / (2 * math.pi) / c.n_atoms
+    dE = (c.N_d / len(pts)) * float(np.abs(w @ (d32 - d64)).sum()) / (2 * math.pi) / c.n_atoms
     assert dE <= 1e-5, dE
 
 
