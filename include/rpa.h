@@ -176,6 +176,25 @@ rpa_status lanczos_energy_density(rpa_handle h, int32_t n_omega, const double* o
                                   int32_t n_pts, const int64_t* point_idx, int32_t n_lanczos,
                                   double* d, rpa_stats* st, void* stream);
 
+/* Block Lanczos quadrature over groups of grid points (the block operations
+ * for several points proposed in the Conclusions and Future Work section):
+ * for each frequency the points are taken in consecutive groups of `block`
+ * (the last group of a frequency holds the remainder), each group runs
+ * n_lanczos steps of block Lanczos on nu^1/2 chi0(i omega_k) nu^1/2 from
+ * Q_1 = [e_j ...] with full reorthogonalisation (two classical
+ * Gram-Schmidt passes) and a thin QR per step, and
+ * d[k][p] = [E_1^T f(T) E_1]_ii for the group's i-th point, T the block
+ * tridiagonal matrix.  A group stops early (T truncated, RPA_W_BREAKDOWN)
+ * when a diagonal entry of the QR factor is at most the handle's Lanczos
+ * breakdown threshold times the largest |A_k| entry.  block = 1 is the
+ * estimate of lanczos_energy_density.  Each group costs n_lanczos chi0
+ * applications per point, as the scalar path does.  block in [1, 8],
+ * n_lanczos * block <= 64 (RPA_E_ARG otherwise); arrays as for
+ * lanczos_energy_density.  Batches run eagerly (no graph replay). */
+rpa_status lanczos_energy_density_block(rpa_handle h, int32_t n_omega, const double* omega,
+                                        int32_t n_pts, const int64_t* point_idx, int32_t n_lanczos,
+                                        int32_t block, double* d, rpa_stats* st, void* stream);
+
 /* Coarse-to-fine interpolation I_g (section "Interpolating Diagonal
  * Entries"): coarse values live on the origin-aligned sublattice of points
  * whose three indices are multiples of `stride` (stride divides every n_d).

@@ -97,6 +97,8 @@ _SIGS = {
     "chi0_apply": [_VP, _D, _I32, _VP, _VP, _I32, ctypes.POINTER(Stats), _VP],
     "chi0_apply_noalloc": [_VP, _D, _I32, _VP, _VP, _I32, ctypes.POINTER(Stats), _VP],
     "lanczos_energy_density": [_VP, _I32, _VP, _I32, _VP, _I32, _VP, ctypes.POINTER(Stats), _VP],
+    "lanczos_energy_density_block": [_VP, _I32, _VP, _I32, _VP, _I32, _I32, _VP, ctypes.POINTER(Stats),
+                                     _VP],
     "interpolate": [_VP, _I32, _I32, _I32, _VP, _VP, _VP],
     "rpa_energy_from_coarse": [_VP, _I32, _VP, _I32, _I32, _VP, _VP, _VP, _VP],
     "correlation_energy": [_VP, _I32, _VP, _VP, _I32, _I32, _I32, _VP, _VP,
@@ -294,6 +296,19 @@ class Handle:
                                             pts.ctypes.data, int(n_lanczos), _ptr(d),
                                             ctypes.byref(st), _stream(stream)),
                "lanczos_energy_density")
+        return d, st.as_dict()
+
+    def lanczos_energy_density_block(self, omegas, points, n_lanczos, block, stream=None):
+        """Block Lanczos quadrature over consecutive groups of `block` points
+        per frequency; d[k, p] as lanczos_energy_density."""
+        om = np.ascontiguousarray(omegas, dtype=np.float64)
+        pts = np.ascontiguousarray(points, dtype=np.int64)
+        d = self._torch.empty((om.size, pts.size), dtype=self._torch.float64, device="cuda")
+        st = Stats()
+        _check(lib().lanczos_energy_density_block(self._h, om.size, om.ctypes.data, pts.size,
+                                                  pts.ctypes.data, int(n_lanczos), int(block), _ptr(d),
+                                                  ctypes.byref(st), _stream(stream)),
+               "lanczos_energy_density_block")
         return d, st.as_dict()
 
     def interpolate(self, kind, stride, coarse, stream=None):

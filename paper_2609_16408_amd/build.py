@@ -18,7 +18,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_NAME = "librpa_mi355x.so"
 LIB_PATH = os.path.join(PKG, LIB_NAME)
 SOURCES = ["engine.hip", "cocg.hip", "cocg_nl.hip", "cocg_pc.hip", "kernels.hip", "server.hip",
-           "precond.hip"]
+           "precond.hip", "block_lanczos.hip"]
 ARCH = "gfx950"
 
 

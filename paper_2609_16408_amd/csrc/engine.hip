@@ -68,6 +68,10 @@ struct rpa_ctx {
   DevBuf x64, slots, u64, racc, vtmp, tmpA, Q, alpha, beta, mlen, active, order, iters, cycles,
       status, counter, stats, omega_b, pos_b, idx_b, gpart, G, dhat, partials, interp_m, shifts, fail,
       faillist, obin, ostats;
+  // block Lanczos: per group first column, size, active flag, block count,
+  // max |A| entry, normalisation; the A_k and B_k blocks; contraction
+  // coefficients and their partial sums
+  DevBuf bgcol, bgsz, bgact, bgm, bamax, bscale, Ablk, Bblk, bC, bpart;
   // per-frequency iteration statistics of the current / last call
   int stat_bins = 0;                 // 0: not recorded
   std::vector<double> stat_omega;    // frequency of each bin
@@ -1452,6 +1456,172 @@ rpa_status lanczos_energy_density(rpa_handle h, int32_t n_omega, const double* o
   // Lanczos truncations: count mlen < m over the last batch only is not enough;
   // the tridiagonal kernel flags QL failures, truncations are tracked below.
   return end_stats(h, s, st, t0, P_total * (long long)h->nocc * m, 0);
+}
+
+}  // extern "C"
+
+namespace {
+
+// One batch of G groups (columns gcol[g] .. gcol[g] + gsz[g] - 1, at most
+// bmax each) through m block Lanczos steps, then the block Gauss rule into
+// d[pos_b[column]].  Eager launches only.
+rpa_status enqueue_block_batch(rpa_ctx* h, int nb, int G, int bmax, int m, double* d, hipStream_t s) {
+  const long long N = h->N;
+  const int pmax = std::max(m, 2) * kMaxLzBlock;
+  constexpr size_t S = (size_t)kMaxLzBlock * kMaxLzBlock;
+  double* Q = P<double>(h->Q);
+  double* W = P<double>(h->u64);
+  const int* gcol = P<int>(h->bgcol);
+  const int* gsz = P<int>(h->bgsz);
+  int* gact = P<int>(h->bgact);
+  double* C = P<double>(h->bC);
+  double* part = P<double>(h->bpart);
+  double* Ab = P<double>(h->Ablk);
+  double* Bb = P<double>(h->Bblk);
+  HIPCHK(h, launch_fill_d(Q, 0.0, (long long)m * nb * N, s));
+  HIPCHK(h, launch_set_onehot(Q, N, P<long long>(h->idx_b), nb, s));
+  HIPCHK(h, launch_fill_i(P<int>(h->active), 1, nb, s));
+  HIPCHK(h, launch_fill_i(gact, 1, G, s));
+  HIPCHK(h, launch_fill_i(P<int>(h->bgm), 0, G, s));
+  HIPCHK(h, launch_fill_d(P<double>(h->bamax), 0.0, G, s));
+  HIPCHK(h, launch_fill_d(Ab, 0.0, (long long)G * m * S, s));
+  HIPCHK(h, launch_fill_d(Bb, 0.0, (long long)G * m * S, s));
+  static const std::vector<double> none;
+  const BVSet Wall{W, 0, 1, 0, 0};
+  for (int k = 0; k < m; ++k) {
+    double* qk = Q + (size_t)k * nb * N;
+    rpa_status r = coulomb(h, 1, nb, qk, W, s);
+    if (r != RPA_OK) return r;
+    r = sternheimer_batch(h, nb, none, P<int>(h->active), s, false, true);
+    if (r != RPA_OK) return r;
+    r = coulomb(h, 1, nb, P<double>(h->racc), W, s);
+    if (r != RPA_OK) return r;
+    // A_k = sym(Q_k^T W); W -= Q_{k-1} B_{k-1}^T + Q_k A_k
+    HIPCHK(h, launch_bgram(BVSet{Q, k, 1, 0, 0}, Wall, bmax, nb, N, G, gcol, gsz, gact, pmax, part, C, s));
+    HIPCHK(h, launch_bstep_diag(G, k, m, gsz, gact, pmax, C, Ab, Bb, P<double>(h->bamax), P<int>(h->bgm), s));
+    const BVSet prev2{Q, k > 0 ? k - 1 : 0, k > 0 ? 2 : 1, 0, 0};
+    HIPCHK(h, launch_bcombine(prev2, Wall, nb, N, G, gcol, gsz, gact, pmax, C, s));
+    // two classical Gram-Schmidt passes against every stored block
+    const BVSet stored{Q, 0, k + 1, 0, 0};
+    for (int pass = 0; pass < 2; ++pass) {
+      HIPCHK(h, launch_bgram(stored, Wall, (k + 1) * bmax, nb, N, G, gcol, gsz, gact, pmax, part, C, s));
+      HIPCHK(h, launch_bcombine(stored, Wall, nb, N, G, gcol, gsz, gact, pmax, C, s));
+    }
+    if (k == m - 1) break;
+    // Q_{k+1} B_k = W, column by column (two projection passes each)
+    for (int j = 0; j < bmax; ++j) {
+      const BVSet wj{W, 0, 1, j, 1};
+      if (j > 0) {
+        const BVSet done{Q, k + 1, 1, 0, j};
+        for (int pass = 0; pass < 2; ++pass) {
+          HIPCHK(h, launch_bgram(done, wj, j, nb, N, G, gcol, gsz, gact, pmax, part, C, s));
+          HIPCHK(h, launch_bqr_acc(G, k, m, j, gsz, gact, pmax, C, Bb, s));
+          HIPCHK(h, launch_bcombine(done, wj, nb, N, G, gcol, gsz, gact, pmax, C, s));
+        }
+      }
+      HIPCHK(h, launch_bgram(wj, wj, 1, nb, N, G, gcol, gsz, gact, pmax, part, C, s));
+      HIPCHK(h, launch_bqr_norm(G, k, m, j, gcol, gsz, gact, pmax, C, Bb, P<double>(h->bamax), h->lz_brk,
+                                P<double>(h->bscale), P<int>(h->active), s));
+      HIPCHK(h, launch_bqr_scale(Q, W, nb, N, G, k, j, gcol, gsz, gact, P<double>(h->bscale), s));
+    }
+    if (h->progress) {
+      HIPCHK(h, hipStreamSynchronize(s));
+      std::fprintf(stderr, "[rpa] block batch %lld (%d groups): Lanczos step %d/%d done at %.1f s\n",
+                   h->progress_batch, G, k + 1, m, now_s() - h->progress_t0);
+      std::fflush(stderr);
+    }
+  }
+  HIPCHK(h, launch_block_quad(G, m, gcol, gsz, P<int>(h->bgm), Ab, Bb, P<long long>(h->pos_b), d,
+                              P<int>(h->fail), s));
+  return RPA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rpa_status lanczos_energy_density_block(rpa_handle h, int32_t n_omega, const double* omega,
+                                        int32_t n_pts, const int64_t* point_idx, int32_t n_lanczos,
+                                        int32_t block, double* d, rpa_stats* st, void* stream) {
+  rpa_status u = usable(h);
+  if (u != RPA_OK) return u;
+  ARG_CHECK(n_omega >= 1 && n_pts >= 1 && omega && point_idx && d, "bad arguments");
+  ARG_CHECK(block >= 1 && block <= kMaxLzBlock, "block must be in [1, 8]");
+  ARG_CHECK(n_lanczos >= 1 && (long long)n_lanczos * block <= kMaxLanczos,
+            "n_lanczos * block must be in [1, 64]");
+  for (int k = 0; k < n_omega; ++k) ARG_CHECK(omega[k] > 0 && std::isfinite(omega[k]), "omega must be positive");
+  for (int p = 0; p < n_pts; ++p) ARG_CHECK(point_idx[p] >= 0 && point_idx[p] < h->N, "point index out of range");
+  const double t0 = now_s();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const long long N = h->N;
+  const int m = n_lanczos;
+  // groups: consecutive points at one frequency, the last of each frequency ragged
+  struct Grp { int k, p0, b; };
+  std::vector<Grp> groups;
+  for (int k = 0; k < n_omega; ++k)
+    for (int p0 = 0; p0 < n_pts; p0 += block) groups.push_back({k, p0, std::min(block, n_pts - p0)});
+  int B = h->batch > 0 ? h->batch : 64;
+  B = std::max(B, (int)block);
+  B = (int)std::min<long long>(B, (long long)n_omega * n_pts);
+  rpa_status r = begin_stats(h, s, std::vector<double>(omega, omega + n_omega), B);
+  if (r != RPA_OK) return r;
+  const int gmax = B;
+  const int pmax = std::max(m, 2) * kMaxLzBlock;
+  constexpr size_t S = (size_t)kMaxLzBlock * kMaxLzBlock;
+  ENSURE(h, h->Q, (size_t)m * B * N * sizeof(double));
+  ENSURE(h, h->u64, (size_t)B * N * sizeof(double));
+  ENSURE(h, h->active, (size_t)B * sizeof(int));
+  ENSURE(h, h->omega_b, (size_t)B * sizeof(double));
+  ENSURE(h, h->pos_b, (size_t)B * sizeof(long long));
+  ENSURE(h, h->idx_b, (size_t)B * sizeof(long long));
+  ENSURE(h, h->bgcol, (size_t)gmax * sizeof(int));
+  ENSURE(h, h->bgsz, (size_t)gmax * sizeof(int));
+  ENSURE(h, h->bgact, (size_t)gmax * sizeof(int));
+  ENSURE(h, h->bgm, (size_t)gmax * sizeof(int));
+  ENSURE(h, h->bamax, (size_t)gmax * sizeof(double));
+  ENSURE(h, h->bscale, (size_t)gmax * sizeof(double));
+  ENSURE(h, h->Ablk, (size_t)gmax * m * S * sizeof(double));
+  ENSURE(h, h->Bblk, (size_t)gmax * m * S * sizeof(double));
+  ENSURE(h, h->bC, (size_t)gmax * pmax * kMaxLzBlock * sizeof(double));
+  ENSURE(h, h->bpart, (size_t)gmax * pmax * kMaxLzBlock * bgram_chunks(N) * sizeof(double));
+  std::vector<double> om;
+  std::vector<long long> pos, idx;
+  std::vector<int> bin, gcol, gsz;
+  h->progress_t0 = t0;
+  h->progress_batch = 0;
+  size_t gi = 0;
+  while (gi < groups.size()) {
+    // whole groups into one batch of at most B columns
+    om.clear(); pos.clear(); idx.clear(); bin.clear(); gcol.clear(); gsz.clear();
+    int bmax = 0;
+    while (gi < groups.size() && (int)om.size() + groups[gi].b <= B) {
+      const Grp& g = groups[gi++];
+      gcol.push_back((int)om.size());
+      gsz.push_back(g.b);
+      bmax = std::max(bmax, g.b);
+      for (int c = 0; c < g.b; ++c) {
+        om.push_back(omega[g.k]);
+        pos.push_back((long long)g.k * n_pts + g.p0 + c);
+        idx.push_back(point_idx[g.p0 + c]);
+        bin.push_back(g.k);
+      }
+    }
+    const int nb = (int)om.size(), G = (int)gcol.size();
+    ++h->progress_batch;
+    HIPCHK(h, hipMemcpyAsync(h->omega_b.p, om.data(), nb * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->obin.p, bin.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->pos_b.p, pos.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->idx_b.p, idx.data(), nb * sizeof(long long), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->bgcol.p, gcol.data(), G * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->bgsz.p, gsz.data(), G * sizeof(int), hipMemcpyHostToDevice, s));
+    r = upload_order_for(h, nb, om, s);
+    if (r != RPA_OK) return r;
+    r = enqueue_block_batch(h, nb, G, bmax, m, d, s);
+    if (r != RPA_OK) return r;
+    // the host vectors above are reused by the next batch: their copies must have landed
+    HIPCHK(h, hipStreamSynchronize(s));
+  }
+  return end_stats(h, s, st, t0, (long long)n_omega * n_pts * h->nocc * m, 0);
 }
 
 rpa_status interpolate(rpa_handle h, int32_t kind, int32_t stride, int32_t n_fields,

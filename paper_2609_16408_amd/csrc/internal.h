@@ -183,6 +183,36 @@ hipError_t launch_accumulate(const double* psi, const double2* x64, int B, int n
                              const int* active, double* racc, hipStream_t s);
 
 // Q layout [m_total][B][N]
+// Block Lanczos over groups of batch columns (block_lanczos.hip).  A vector
+// set of a group: blocks blk0 .. blk0 + n_blk - 1 of the basis at `base`
+// (layout [block][batch column][N]), columns c0 .. c0 + ncol - 1 of the
+// group (ncol <= 0: up to the group's size), clipped to the group's size.
+constexpr int kMaxLzBlock = 8;           // largest block size
+constexpr int kBgramChunk = 4096;        // grid rows per partial dot product
+struct BVSet {
+  double* base;
+  int blk0, n_blk, c0, ncol;
+};
+int bgram_chunks(long long N);
+hipError_t launch_bgram(const BVSet& X, const BVSet& Y, int max_x, int B, long long N, int G,
+                        const int* gcol, const int* gsz, const int* gact, int pmax, double* part,
+                        double* C, hipStream_t s);
+hipError_t launch_bcombine(const BVSet& X, const BVSet& Y, int B, long long N, int G, const int* gcol,
+                           const int* gsz, const int* gact, int pmax, const double* C, hipStream_t s);
+hipError_t launch_bstep_diag(int G, int k, int m, const int* gsz, const int* gact, int pmax, double* C,
+                             double* Ablk, const double* Bblk, double* amax, int* gm, hipStream_t s);
+hipError_t launch_bqr_acc(int G, int k, int m, int j, const int* gsz, const int* gact, int pmax,
+                          const double* C, double* Bblk, hipStream_t s);
+hipError_t launch_bqr_norm(int G, int k, int m, int j, const int* gcol, const int* gsz, int* gact,
+                           int pmax, const double* C, double* Bblk, const double* amax, double brk,
+                           double* scale, int* active, hipStream_t s);
+hipError_t launch_bqr_scale(double* Q, const double* W, int B, long long N, int G, int k, int j,
+                            const int* gcol, const int* gsz, const int* gact, const double* scale,
+                            hipStream_t s);
+hipError_t launch_block_quad(int G, int m, const int* gcol, const int* gsz, const int* gm,
+                             const double* Ablk, const double* Bblk, const long long* pos, double* dout,
+                             int* fail, hipStream_t s);
+
 hipError_t launch_lanczos_step(int k, int m_total, int B, long long N, double* Q, double* v,
                                double* alpha, double* beta, int* mlen, int* active, double brk,
                                hipStream_t s);
