@@ -607,6 +607,33 @@ def test_iteration_stats_per_frequency(P, tiny):
     assert means[0] > means[-1]
 
 
+def test_iteration_stats_count_reliable_updates_per_frequency(P, tiny):
+    """FP32 + refinement: the per-frequency reliable-update counts add up to
+    the call's total (no solve is handed over here), and every frequency
+    has some (convergence is only accepted on an FP64 residual)."""
+    om, _ = O.frequency_rule(4)
+    pts = np.array([0, 5, 333, 1000])
+    h = _handle(P, tiny, precision="fp32_refine", stern_tol=1e-8)
+    _, st = h.lanczos_energy_density(om, pts, 4)
+    stats = h.last_iteration_stats()
+    h.close()
+    assert st["n_fp64_fallback"] == 0
+    assert sum(s["refine_cycles"] for s in stats) == st["refine_cycles"]
+    assert all(s["refine_cycles"] > 0 for s in stats)
+
+
+def test_progress_prints_one_line_per_lanczos_step(P, tiny, capfd):
+    """rpa_setup_params.progress: one stderr line per Lanczos step of a batch."""
+    om, _ = O.frequency_rule(2)
+    pts = np.array([0, 5, 333])
+    h = _handle(P, tiny, stern_tol=1e-8, progress=True)
+    h.lanczos_energy_density(om, pts, 3)
+    h.close()
+    err = capfd.readouterr().err
+    lines = [l for l in err.splitlines() if l.startswith("[rpa] batch")]
+    assert len(lines) == 3 and "Lanczos step 3/3 done" in lines[-1], err
+
+
 def _ratio_sequence(alpha, beta):
     """beta_k / max_{i<=k} |alpha_i|: the quantity the breakdown test compares."""
     amax = np.maximum.accumulate(np.abs(alpha))

@@ -177,12 +177,18 @@ def test_preconditioner_frequency_window(P, pcells):
     om = np.array([0.0203, 0.69, 3.22])
     pts = np.array([0, 333, 1000, 1727])
     runs = {}
+    split = {}
     for key, kw in (("plain", {}), ("all", {"precond": True}),
                     ("window", {"precond": True, "precond_window": (0.5, 5.0)})):
         h = P.handle_for_cell(c, stern_tol=1e-10, **kw)
         d, st = h.lanczos_energy_density(om, pts, 6)
         runs[key] = (d, h.last_iteration_stats())
+        split[key] = h.last_cocg_split()
         h.close()
+    # the launch time is attributed to the kernels that ran
+    assert split["plain"]["plain"] > 0 and split["plain"]["precond"] == 0
+    assert split["all"]["plain"] == 0 and split["all"]["precond"] > 0
+    assert split["window"]["plain"] > 0 and split["window"]["precond"] > 0
     d0, s0 = runs["plain"]
     d1, s1 = runs["all"]
     dw, sw = runs["window"]
