@@ -26,7 +26,8 @@ HBM_PEAK_GBPS = 8000.0
 # the kernel's traffic also depends on the engine's defaults (reliable-update
 # factor, processing order), so the engine source is part of the key
 COCG_SRC = [os.path.join(ROOT, "paper_2609_16408_amd", "csrc", f)
-            for f in ("cocg_impl.h", "cocg.hip", "engine.hip")]
+            for f in ("cocg_impl.h", "precond_impl.h", "internal.h", "cocg.hip", "cocg_nl.hip",
+                      "cocg_pc.hip", "engine.hip")]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_cocg_si64_hbm_traffic.md")
 CALIB_BYTES = 1 << 30
 
