@@ -561,6 +561,8 @@ def test_si64_bench_configuration_fp32_matches_fp64(P, si64):
     d32, d64 = d["fp32_refine"].cpu().numpy(), d["fp64"].cpu().numpy()
     assert (d64 <= 0).all() and (d32 <= 0).all()
     dE = (c.N_d / len(pts)) * float(np.abs(w @ (d32 - d64)).sum()) / (2 * math.pi) / c.n_atoms
+    print(f"si64 bench configuration: max |d32 - d64| = {np.abs(d32 - d64).max():.2e}, "
+          f"extrapolated |dE|/atom = {dE:.2e}", flush=True)
     assert dE <= 1e-5, dE
 
 

@@ -98,3 +98,23 @@ def test_status_reports_admission_high_water():
     assert st["in_use"] == 0
     assert st["high_water"] >= idle["high_water"] + max(i["footprint"] for i in infos)
     s.close()
+
+
+def test_cells_added_while_jobs_run():
+    """Cells added while workers run jobs of earlier cells: every job
+    finishes, on the cell it names (workers keep the cell they took under the
+    server's lock, so growing the cell table cannot move it under them)."""
+    s, cid = _server(3)
+    ids = [(cid, s.submit(cid, 0.5, np.arange(16), 4)) for _ in range(3)]
+    for k in range(40):
+        c = s.add_cell((24, 24, 24 + 12 * (k % 2)), (10.26,) * 3, None, None,
+                       np.linspace(-0.5, -0.4, 16))
+        ids.append((c, s.submit(c, 0.5, np.arange(8), 2)))
+    infos = [(c, s.wait(j)[1]) for c, j in ids]
+    s.close()
+    assert all(i["status"] == 0 for _, i in infos)
+    # footprints follow the grid of the cell each job named
+    fp = {}
+    for c, i in infos[3:]:
+        fp.setdefault(c % 2, set()).add(i["footprint"])
+    assert len(fp) == 2 and all(len(v) == 1 for v in fp.values()) and fp[0] != fp[1]
