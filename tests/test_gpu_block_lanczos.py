@@ -8,6 +8,7 @@ the 2-point frequency rule, so block 3 leaves a ragged group of 1 and block
 4 one of 3.  Si8-like cell: accuracy per chi0 application of block and
 scalar estimates against the stored N_l = 30 oracle values.
 """
+import math
 import os
 
 import numpy as np
@@ -150,3 +151,70 @@ def test_si8_block_accuracy_per_chi0_application(P):
     for m in (2, 4):
         assert errs[m][1] <= errs[m][0] * 1.05
     assert errs[4][0] < errs[2][0] and errs[4][1] < errs[2][1]
+
+
+def _block_ratio_sequences(ham, coul, c, om, pts, block, m):
+    """Per (frequency, group): min |diag B_k| / max |A_0..A_k entries| of the
+    oracle's untruncated block Lanczos (the quantity its breakdown test
+    compares), for k < m - 1."""
+    seqs = []
+    for w in om:
+        A = O.nuhalf_chi0_nuhalf(ham, coul, c.psi, c.eps, w, tol=1e-10)
+        ap = lambda X, A=A: np.stack([A(X[:, i]) for i in range(X.shape[1])], axis=1)
+        for g0 in range(0, len(pts), block):
+            grp = pts[g0:g0 + block]
+            Q1 = np.zeros((c.N_d, len(grp)))
+            Q1[grp, np.arange(len(grp))] = 1.0
+            Ab, Bb, _ = O.block_lanczos(ap, Q1, m, breakdown_rel=0.0)
+            amax, r = 0.0, []
+            for k, Bk in enumerate(Bb):
+                amax = max(amax, float(np.abs(Ab[k]).max()))
+                r.append(float(np.abs(np.diag(Bk)).min()) / amax)
+            seqs.append(np.array(r))
+    return seqs
+
+
+def test_block_lanczos_breakdown_truncates_like_the_oracle(P, tiny, tiny_ops):
+    """Block Lanczos truncation (reading R18) forced from the host: the
+    threshold sits at the geometric middle of the widest gap (at least 2x)
+    of the oracle's ratio sequences that truncates some groups but not all,
+    so both sides stop the same groups at the same step (their ratios agree
+    to ~1e-9).  The truncated estimates equal the oracle's, differ from the
+    untruncated ones, and the call warns."""
+    ham, coul = tiny_ops
+    om, m, block = np.array([0.0203, 0.69]), 8, 3
+    pts = np.array([0, 100, 777, 1500, 1001, 333])
+    seqs = _block_ratio_sequences(ham, coul, tiny, om, pts, block, m)
+    allr = np.sort(np.concatenate(seqs))
+    best, thr = 0.0, None
+    for lo, hi in zip(allr[:-1], allr[1:]):
+        t = math.sqrt(lo * hi)
+        cut = [bool(np.any(r <= t)) for r in seqs]
+        if any(cut) and not all(cut) and hi / lo > best:
+            best, thr = hi / lo, t
+    assert thr is not None and best > 2.0, (best, seqs)
+    n_cut = sum(bool(np.any(r <= thr)) for r in seqs)
+    h = P.handle_for_cell(tiny, precision="fp64", stern_tol=1e-10, batch=8, lanczos_breakdown=thr)
+    with pytest.warns(P.RPAWarning):
+        d, st = h.lanczos_energy_density_block(om, pts, m, block)
+    h.close()
+    assert st["n_breakdown"] == n_cut
+    ref = np.zeros((len(om), len(pts)))
+    full = np.zeros_like(ref)
+    for k, w in enumerate(om):
+        A = O.nuhalf_chi0_nuhalf(ham, coul, tiny.psi, tiny.eps, w, tol=1e-10)
+        ap = lambda X, A=A: np.stack([A(X[:, i]) for i in range(X.shape[1])], axis=1)
+        for g0 in range(0, len(pts), block):
+            grp = pts[g0:g0 + block]
+            Q1 = np.zeros((tiny.N_d, len(grp)))
+            Q1[grp, np.arange(len(grp))] = 1.0
+            Ab, Bb, broke = O.block_lanczos(ap, Q1, m, breakdown_rel=thr)
+            ref[k, g0:g0 + len(grp)] = O.block_quadrature(Ab, Bb)
+            Ab, Bb, _ = O.block_lanczos(ap, Q1, m, breakdown_rel=0.0)
+            full[k, g0:g0 + len(grp)] = O.block_quadrature(Ab, Bb)
+    d = d.cpu().numpy()
+    err = np.abs(d - ref).max()
+    print(f"block breakdown: threshold {thr:.2e} (gap x{best:.1f}), {n_cut} of {len(seqs)} groups "
+          f"truncated, max |d - d_oracle| = {err:.2e}", flush=True)
+    assert err <= 1e-9, err
+    assert np.abs(ref - full).max() > 1e-12
