@@ -112,6 +112,18 @@ typedef struct {
                                  step of a batch and prints one line per step to stderr
                                  (for long runs; eager batches only: a replayed graph
                                  prints nothing) */
+  int32_t n_extra;            /* extra eigenpairs of H above the occupied ones that widen
+                                 the Galerkin initial guess of every Sternheimer solve
+                                 (Implementation section: the guess is the exact solution
+                                 inside the projection space): x0 = sum_m psi_m (dV psi_m^T b)
+                                 / (eps_m - eps_n - i omega) over the occupied and the extra
+                                 states, so the initial residual has no component along the
+                                 low unoccupied states that slow COCG at small omega.  The
+                                 solutions and chi0 are unchanged (same stopping rule).
+                                 0 = occupied states only; at most 1024. */
+  const double* psi_extra;    /* [dev] [n_extra][N_d] eigenvectors, dV*sum(psi^2) = 1,
+                                 orthogonal to the occupied ones (copied at setup) */
+  const double* eps_extra;    /* [host] [n_extra] their eigenvalues (Ha) */
 } rpa_setup_params;
 
 typedef struct {

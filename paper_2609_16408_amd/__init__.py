@@ -48,6 +48,7 @@ class SetupParams(ctypes.Structure):
         ("lanczos_breakdown", ctypes.c_double), ("precond", ctypes.c_int32),
         ("precond_omega_min", ctypes.c_double), ("precond_omega_max", ctypes.c_double),
         ("progress", ctypes.c_int32),
+        ("n_extra", ctypes.c_int32), ("psi_extra", ctypes.c_void_p), ("eps_extra", ctypes.c_void_p),
     ]
 
 
@@ -182,7 +183,7 @@ class Handle:
     def __init__(self, n, L, v_loc, psi, eps, precision="fp64", stern_tol=1e-10,
                  stern_maxit=20000, batch=0, tile_y=0, slots_per_cu=0, inner_tol=0.0,
                  hbm_budget=0, use_graph=False, proj=None, fp32_maxit=0, lanczos_breakdown=0.0,
-                 precond=False, precond_window=None, progress=False, stream=None):
+                 precond=False, precond_window=None, progress=False, extra=None, stream=None):
         import torch
         self._torch = torch
         dev = torch.device("cuda")
@@ -220,6 +221,17 @@ class Handle:
         if precond_window is not None:
             prm.precond_omega_min, prm.precond_omega_max = (float(v) for v in precond_window)
         prm.progress = 1 if progress else 0
+        if extra is not None:
+            # extra eigenpairs (psi_extra [n_x][N], eps_extra [n_x]) widen the Galerkin guess
+            px, ex = extra
+            px = torch.as_tensor(np.ascontiguousarray(px, dtype=np.float64)).to(dev) \
+                if not torch.is_tensor(px) else px.to(dev, torch.float64).contiguous()
+            ex = np.ascontiguousarray(ex, dtype=np.float64)
+            assert px.shape == (ex.size, self.N)
+            prm.n_extra = int(ex.size)
+            prm.psi_extra = px.data_ptr()
+            prm.eps_extra = ex.ctypes.data
+            self._extra_keep = (px, ex)
         h = ctypes.c_void_p()
         _check(lib().rpa_setup(ctypes.byref(prm), _stream(stream), ctypes.byref(h)), "rpa_setup")
         del keep

@@ -32,6 +32,7 @@ struct rpa_ctx {
   double L[3], h[3], dV;
   long long N;
   int nocc;
+  int ngal;                          // Galerkin states: the occupied ones, then the extra ones
   int precision;
   double tol;
   int maxit;
@@ -329,17 +330,19 @@ rpa_status sternheimer_batch(rpa_ctx* h, int B, const std::vector<double>& omega
   const int nocc = h->nocc;
   const bool refine = h->precision == RPA_FP32_REFINE;
   const int n_items = B * nocc;
-  // Galerkin initial guess: the Gram contraction C = h^3 Psi^T diag(u) Psi
-  // runs on the FP64 matrix cores (k_gram); the energy denominators
-  // (k_gram_finish) and the expansion x0 = Psi G (k_expand) on vector FP64
+  // Galerkin initial guess over the ngal states (occupied, then any extra
+  // eigenpairs): the Gram contraction C = h^3 Psi_g^T diag(u) Psi runs on the
+  // FP64 matrix cores (k_gram); the energy denominators (k_gram_finish) and
+  // the expansion x0 = Psi_g G (k_expand) on vector FP64
   const int n_chunks = gram_chunks(N);
-  ENSURE(h, h->gpart, (size_t)B * n_chunks * nocc * nocc * sizeof(double));
-  ENSURE(h, h->G, (size_t)B * nocc * nocc * sizeof(double2));
+  const int ng = h->ngal;
+  ENSURE(h, h->gpart, (size_t)B * n_chunks * ng * nocc * sizeof(double));
+  ENSURE(h, h->G, (size_t)B * ng * nocc * sizeof(double2));
   ENSURE(h, h->x64, (size_t)n_items * N * sizeof(double2));
-  HIPCHK(h, launch_gram(h->psi64, P<double>(h->u64), B, nocc, N, n_chunks, P<double>(h->gpart), s));
-  HIPCHK(h, launch_gram_finish(P<double>(h->gpart), B, nocc, n_chunks, h->dV, h->eps_d,
+  HIPCHK(h, launch_gram(h->psi64, P<double>(h->u64), B, nocc, ng, N, n_chunks, P<double>(h->gpart), s));
+  HIPCHK(h, launch_gram_finish(P<double>(h->gpart), B, nocc, ng, n_chunks, h->dV, h->eps_d,
                                P<double>(h->omega_b), P<double2>(h->G), s));
-  HIPCHK(h, launch_expand(h->psi64, P<double2>(h->G), B, nocc, N, P<double2>(h->x64), s));
+  HIPCHK(h, launch_expand(h->psi64, P<double2>(h->G), B, nocc, ng, N, P<double2>(h->x64), s));
 
   ENSURE(h, h->order, 2 * (size_t)n_items * sizeof(int));
   ENSURE(h, h->iters, (size_t)n_items * sizeof(int));
@@ -766,7 +769,8 @@ uint64_t lanczos_workspace_bytes(const rpa_setup_params& p, int B, int n_lanczos
   // Lanczos basis, start/iteration vectors, recurrence scalars and bookkeeping
   uint64_t bytes = m * b * N * 8 + b * N * 8 + 2 * b * m * 8 + 2 * b * 4 + 4 * b * 8 + 64 + 16;
   bytes += 2 * b * N * 8;                                   // nu^1/2 transform buffers
-  bytes += b * (uint64_t)gram_chunks((long long)N) * nocc * nocc * 8 + b * nocc * nocc * 16;
+  const uint64_t ngal = nocc + (uint64_t)std::max(0, p.n_extra);
+  bytes += b * (uint64_t)gram_chunks((long long)N) * ngal * nocc * 8 + b * ngal * nocc * 16;
   bytes += items * N * 16;                                  // Sternheimer solutions (FP64)
   bytes += items * 4 * (refine ? 6 : 5) + 64 * 4;           // two order lists, counts, status, hand-over list
   bytes += b * N * 8;                                       // accumulated density response
@@ -800,6 +804,10 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   ARG_CHECK(p->fd_radius == kRadius, "fd_radius must be 6 (12th-order FD)");
   const long long N = (long long)p->n[0] * p->n[1] * p->n[2];
   ARG_CHECK(p->n_occ >= 1 && p->n_occ < N, "n_occ must be in [1, N_d)");
+  ARG_CHECK(p->n_extra >= 0 && p->n_extra <= 1024 && (long long)p->n_occ + p->n_extra < N,
+            "n_extra must be in [0, 1024] with n_occ + n_extra < N_d");
+  ARG_CHECK(p->n_extra == 0 || (p->psi_extra && p->eps_extra), "psi_extra and eps_extra are required with n_extra > 0");
+  for (int i = 0; i < p->n_extra; ++i) ARG_CHECK(std::isfinite(p->eps_extra[i]), "eps_extra must be finite");
   ARG_CHECK(p->v_loc && p->psi && p->eps, "v_loc, psi and eps are required");
   ARG_CHECK(p->precision == RPA_FP64 || p->precision == RPA_FP32_REFINE, "bad precision");
   ARG_CHECK(p->stern_tol > 0 && p->stern_tol < 1, "stern_tol must be in (0, 1)");
@@ -855,6 +863,7 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   h->dV = h->h[0] * h->h[1] * h->h[2];
   h->N = N;
   h->nocc = p->n_occ;
+  h->ngal = p->n_occ + p->n_extra;
   h->precision = p->precision;
   h->tol = p->stern_tol;
   h->maxit = p->stern_maxit;
@@ -923,8 +932,8 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
     return true;
   };
   if (!alloc((void**)&h->v64, N * sizeof(double)) || !alloc((void**)&h->v32, N * sizeof(float)) ||
-      !alloc((void**)&h->psi64, (size_t)h->nocc * N * sizeof(double)) ||
-      !alloc((void**)&h->eps_d, h->nocc * sizeof(double)) ||
+      !alloc((void**)&h->psi64, (size_t)h->ngal * N * sizeof(double)) ||
+      !alloc((void**)&h->eps_d, h->ngal * sizeof(double)) ||
       !alloc((void**)&h->s_half, N * sizeof(double)) || !alloc((void**)&h->s_full, N * sizeof(double)))
     return fail(RPA_E_OOM);
   for (int d = 0; d < 3; ++d)
@@ -1030,6 +1039,11 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   e = hipMemcpyAsync(h->v64, p->v_loc, N * sizeof(double), hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(h->psi64, p->psi, (size_t)h->nocc * N * sizeof(double), hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(h->eps_d, p->eps, h->nocc * sizeof(double), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && p->n_extra > 0)
+    e = hipMemcpyAsync(h->psi64 + (size_t)h->nocc * N, p->psi_extra, (size_t)p->n_extra * N * sizeof(double),
+                       hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && p->n_extra > 0)
+    e = hipMemcpyAsync(h->eps_d + h->nocc, p->eps_extra, p->n_extra * sizeof(double), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(h->s_half, sh.data(), N * sizeof(double), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(h->s_full, sf.data(), N * sizeof(double), hipMemcpyHostToDevice, s);
   for (int d = 0; d < 3 && e == hipSuccess; ++d)
@@ -1211,8 +1225,8 @@ ScratchLayout scratch_layout(rpa_ctx* h, int B, bool symmetrized) {
     add(h->tmpA, b * N * sizeof(double));
     add(h->vtmp, b * N * sizeof(double));
   }
-  add(h->gpart, b * (size_t)gram_chunks(h->N) * nocc * nocc * sizeof(double));
-  add(h->G, b * nocc * nocc * sizeof(double2));
+  add(h->gpart, b * (size_t)gram_chunks(h->N) * h->ngal * nocc * sizeof(double));
+  add(h->G, b * (size_t)h->ngal * nocc * sizeof(double2));
   add(h->x64, items * N * sizeof(double2));
   add(h->order, 2 * items * sizeof(int));
   add(h->iters, items * sizeof(int));

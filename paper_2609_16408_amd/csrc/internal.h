@@ -173,11 +173,11 @@ hipError_t launch_kin_scale(double* a, const double* kin, const double* sig_re,
 hipError_t launch_axis(const double* in, double* out, int B, int d0, int d1, int d2, int axis,
                        int n_out, const double* M, bool trans, const double* scale, hipStream_t s);
 
-hipError_t launch_gram(const double* psi, const double* u, int B, int n_occ, long long N,
+hipError_t launch_gram(const double* psi, const double* u, int B, int n_occ, int ng, long long N,
                        int n_chunks, double* part, hipStream_t s);
-hipError_t launch_gram_finish(const double* part, int B, int n_occ, int n_chunks, double dV,
+hipError_t launch_gram_finish(const double* part, int B, int n_occ, int ng, int n_chunks, double dV,
                               const double* eps, const double* omega, double2* G, hipStream_t s);
-hipError_t launch_expand(const double* psi, const double2* G, int B, int n_occ, long long N,
+hipError_t launch_expand(const double* psi, const double2* G, int B, int n_occ, int ng, long long N,
                          double2* x64, hipStream_t s);
 hipError_t launch_accumulate(const double* psi, const double2* x64, int B, int n_occ, long long N,
                              const int* active, double* racc, hipStream_t s);

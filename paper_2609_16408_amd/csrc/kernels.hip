@@ -105,7 +105,7 @@ constexpr int GK = 16;    // r-block staged in LDS
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) k_gram(const double* __restrict__ psi,
-                                              const double* __restrict__ u, int n_occ,
+                                              const double* __restrict__ u, int n_occ, int ng,
                                               long long N, int n_chunks, int ntn,
                                               double* __restrict__ part) {
   __shared__ double sA[GK][GT + 2];
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(256) k_gram(const double* __restrict__ psi,
       double a = 0.0, bb = 0.0;
       if (r < r1) {
         const double uu = ub[r];
-        if (m0 + i < n_occ) a = psi[(size_t)(m0 + i) * N + r] * uu;
+        if (m0 + i < ng) a = psi[(size_t)(m0 + i) * N + r] * uu;
         if (n0 + i < n_occ) bb = psi[(size_t)(n0 + i) * N + r];
       }
       sA[k][i] = a;
@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(256) k_gram(const double* __restrict__ psi,
     }
     __syncthreads();
   }
-  double* out = part + ((size_t)b * n_chunks + c) * n_occ * n_occ;
+  double* out = part + ((size_t)b * n_chunks + c) * ng * n_occ;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -166,24 +166,25 @@ __global__ void __launch_bounds__(256) k_gram(const double* __restrict__ psi,
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = m0 + qm + i * 16 + lk + 4 * v;
-        if (m < n_occ && n < n_occ) out[(size_t)m * n_occ + n] = acc[i][j][v];
+        if (m < ng && n < n_occ) out[(size_t)m * n_occ + n] = acc[i][j][v];
       }
     }
   }
 }
 
-// part 2: G[b][m][n] = (-dV sum_c part) / (eps_m - eps_n - i omega_b)
-__global__ void k_gram_finish(const double* __restrict__ part, int B, int n_occ, int n_chunks,
+// part 2: G[b][m][n] = (-dV sum_c part) / (eps_m - eps_n - i omega_b), m over the
+// ng Galerkin states (occupied first), n over the occupied ones
+__global__ void k_gram_finish(const double* __restrict__ part, int B, int n_occ, int ng, int n_chunks,
                               double dV, const double* __restrict__ eps,
                               const double* __restrict__ omega, double2* __restrict__ G) {
-  const long long total = (long long)B * n_occ * n_occ;
+  const long long total = (long long)B * ng * n_occ;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
-    const int b = (int)(t / ((long long)n_occ * n_occ));
-    const long long mn = t - (long long)b * n_occ * n_occ;
+    const int b = (int)(t / ((long long)ng * n_occ));
+    const long long mn = t - (long long)b * ng * n_occ;
     const int m = (int)(mn / n_occ), n = (int)(mn % n_occ);
     double s = 0.0;
-    for (int c = 0; c < n_chunks; ++c) s += part[((size_t)b * n_chunks + c) * n_occ * n_occ + mn];
+    for (int c = 0; c < n_chunks; ++c) s += part[((size_t)b * n_chunks + c) * ng * n_occ + mn];
     const double cm = -dV * s;
     const double dr = eps[m] - eps[n];
     const double di = -omega[b];
@@ -192,10 +193,10 @@ __global__ void k_gram_finish(const double* __restrict__ part, int B, int n_occ,
   }
 }
 
-// part 3: x64[(b*n_occ + n)][r] = sum_m psi_m(r) G[b][m][n]
+// part 3: x64[(b*n_occ + n)][r] = sum_m psi_m(r) G[b][m][n], m over the ng states
 // tile 64 r x 64 n; thread (rl = t%16, nl = t/16) owns r = r0+rl+16i, n = n0+nl+16j
 __global__ void __launch_bounds__(256) k_expand(const double* __restrict__ psi,
-                                                const double2* __restrict__ G, int n_occ,
+                                                const double2* __restrict__ G, int n_occ, int ng,
                                                 long long N, double2* __restrict__ x64) {
   __shared__ double sP[16][64 + 1];
   __shared__ double2 sG[16][64 + 1];
@@ -203,19 +204,19 @@ __global__ void __launch_bounds__(256) k_expand(const double* __restrict__ psi,
   const int n0 = blockIdx.y * 64;
   const int b = blockIdx.z;
   const int rl = threadIdx.x & 15, nl = threadIdx.x >> 4;
-  const double2* Gb = G + (size_t)b * n_occ * n_occ;
+  const double2* Gb = G + (size_t)b * ng * n_occ;
   double ar[4][4], ai[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) { ar[i][j] = 0.0; ai[i][j] = 0.0; }
-  for (int mb = 0; mb < n_occ; mb += 16) {
+  for (int mb = 0; mb < ng; mb += 16) {
     for (int e = threadIdx.x; e < 16 * 64; e += 256) {
       const int k = e / 64, i = e % 64;
       const int m = mb + k;
       const long long r = r0 + i;
-      sP[k][i] = (m < n_occ && r < N) ? psi[(size_t)m * N + r] : 0.0;
-      sG[k][i] = (m < n_occ && n0 + i < n_occ) ? Gb[(size_t)m * n_occ + n0 + i] : make_double2(0.0, 0.0);
+      sP[k][i] = (m < ng && r < N) ? psi[(size_t)m * N + r] : 0.0;
+      sG[k][i] = (m < ng && n0 + i < n_occ) ? Gb[(size_t)m * n_occ + n0 + i] : make_double2(0.0, 0.0);
     }
     __syncthreads();
 #pragma unroll 4
@@ -511,24 +512,24 @@ hipError_t launch_kin_scale(double* a, const double* kin, const double* sig_re,
                      sig_re, sig_im, B, N);
   return hipGetLastError();
 }
-hipError_t launch_gram(const double* psi, const double* u, int B, int n_occ, long long N,
+hipError_t launch_gram(const double* psi, const double* u, int B, int n_occ, int ng, long long N,
                        int n_chunks, double* part, hipStream_t s) {
-  const int nt = (n_occ + GT - 1) / GT;
-  hipLaunchKernelGGL(k_gram, dim3(n_chunks, B, nt * nt), dim3(256), 0, s, psi, u, n_occ, N,
-                     n_chunks, nt, part);
+  const int ntm = (ng + GT - 1) / GT, ntn = (n_occ + GT - 1) / GT;
+  hipLaunchKernelGGL(k_gram, dim3(n_chunks, B, ntm * ntn), dim3(256), 0, s, psi, u, n_occ, ng, N,
+                     n_chunks, ntn, part);
   return hipGetLastError();
 }
-hipError_t launch_gram_finish(const double* part, int B, int n_occ, int n_chunks, double dV,
+hipError_t launch_gram_finish(const double* part, int B, int n_occ, int ng, int n_chunks, double dV,
                               const double* eps, const double* omega, double2* G, hipStream_t s) {
-  const long long total = (long long)B * n_occ * n_occ;
-  hipLaunchKernelGGL(k_gram_finish, dim3(grid_for(total, 256)), dim3(256), 0, s, part, B, n_occ,
+  const long long total = (long long)B * ng * n_occ;
+  hipLaunchKernelGGL(k_gram_finish, dim3(grid_for(total, 256)), dim3(256), 0, s, part, B, n_occ, ng,
                      n_chunks, dV, eps, omega, G);
   return hipGetLastError();
 }
-hipError_t launch_expand(const double* psi, const double2* G, int B, int n_occ, long long N,
+hipError_t launch_expand(const double* psi, const double2* G, int B, int n_occ, int ng, long long N,
                          double2* x64, hipStream_t s) {
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)((n_occ + 63) / 64), (unsigned)B);
-  hipLaunchKernelGGL(k_expand, grid, dim3(256), 0, s, psi, G, n_occ, N, x64);
+  hipLaunchKernelGGL(k_expand, grid, dim3(256), 0, s, psi, G, n_occ, ng, N, x64);
   return hipGetLastError();
 }
 hipError_t launch_accumulate(const double* psi, const double2* x64, int B, int n_occ, long long N,

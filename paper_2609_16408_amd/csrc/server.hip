@@ -184,6 +184,11 @@ rpa_status rpa_server_add_cell(rpa_server S, const rpa_setup_params* p, int32_t*
   if (p->n_proj < 0 || p->n_proj > rpa::kMaxProj) return RPA_E_ARG;
   auto c = std::make_unique<CellDef>();
   c->prm = *p;
+  // serving cells keep the occupied Galerkin space (the extra eigenpairs
+  // would need a server copy of their own)
+  c->prm.n_extra = 0;
+  c->prm.psi_extra = nullptr;
+  c->prm.eps_extra = nullptr;
   c->N = (long long)p->n[0] * p->n[1] * p->n[2];
   c->nocc = p->n_occ;
   if (c->N <= 0 || c->nocc < 1 || !p->eps) return RPA_E_ARG;

@@ -58,6 +58,8 @@ class Cell:
     psi: np.ndarray = None      # (n_occ, N_d) float64, h^3 sum psi^2 = 1
     eps: np.ndarray = None      # (n_occ,) float64 ascending
     eps_buffer: np.ndarray = None  # Ritz values of the buffer states above n_occ
+    psi_extra: np.ndarray = None   # converged eigenvectors just above n_occ (ks_orbitals n_extra)
+    eps_extra: np.ndarray = None
     gap: float = float("nan")   # eps_{n_occ+1} - eps_{n_occ}
     eig_residual: float = float("nan")
     proj: dict = None           # nonlocal projectors (CSR), optional
@@ -238,11 +240,13 @@ def _dense_projector_matrix(cell, torch, device):
 
 
 def ks_orbitals(cell: Cell, n_buffer=None, tol=1e-10, degree=24, max_iter=600,
-                device=None, seed=0, verbose=False):
+                device=None, seed=0, verbose=False, n_extra=0):
     """Lowest n_occ eigenpairs of H by Chebyshev-filtered subspace iteration.
 
     Fills cell.psi (h^3-normalised), cell.eps, cell.gap, cell.eig_residual
     (max Euclidean residual ||H x - e x|| of unit-norm x over occupied states).
+    With n_extra > 0 the next n_extra eigenpairs are converged too and kept
+    as cell.psi_extra / cell.eps_extra (the residual then covers them).
     """
     import torch
     if device is None:
@@ -250,6 +254,9 @@ def ks_orbitals(cell: Cell, n_buffer=None, tol=1e-10, degree=24, max_iter=600,
     nocc = cell.n_occ
     if n_buffer is None:
         n_buffer = max(16, int(math.ceil(0.1 * nocc)))
+    if n_extra > 0:
+        n_buffer = max(n_buffer, n_extra + 16)
+    nconv = nocc + n_extra
     k = nocc + n_buffer
     N = cell.N_d
     apply_h = _make_apply_h(cell, torch, device)
@@ -299,7 +306,7 @@ def ks_orbitals(cell: Cell, n_buffer=None, tol=1e-10, degree=24, max_iter=600,
             sigma = sigma2
         X = orth(Y)
         X, HX, ev = rayleigh_ritz(X)
-        R = HX[:nocc] - ev[:nocc, None] * X[:nocc]
+        R = HX[:nconv] - ev[:nconv, None] * X[:nconv]
         res = float(torch.max(torch.linalg.norm(R, dim=1)))
         if verbose and (it % 10 == 0 or verbose >= 2):
             print(f"  chefsi it {it}: max residual {res:.3e}", flush=True)
@@ -314,6 +321,14 @@ def ks_orbitals(cell: Cell, n_buffer=None, tol=1e-10, degree=24, max_iter=600,
             psi[i] = -psi[i]
     cell.psi = np.ascontiguousarray(psi)
     cell.eps = ev_np[:nocc].copy()
+    if n_extra > 0:
+        px = (X[nocc:nconv].cpu().numpy()) / math.sqrt(cell.dV)
+        for i in range(n_extra):
+            j = int(np.argmax(np.abs(px[i])))
+            if px[i, j] < 0:
+                px[i] = -px[i]
+        cell.psi_extra = np.ascontiguousarray(px)
+        cell.eps_extra = ev_np[nocc:nconv].copy()
     cell.eps_buffer = ev_np[nocc:].copy()
     cell.gap = float(ev_np[nocc] - ev_np[nocc - 1])
     cell.eig_residual = res
@@ -347,12 +362,12 @@ PRESETS = {
 }
 
 
-def preset(name: str, orbitals=True, device=None, verbose=False, **overrides) -> Cell:
+def preset(name: str, orbitals=True, device=None, verbose=False, n_extra=0, **overrides) -> Cell:
     cfg = dict(PRESETS[name])
     cfg.update(overrides)
     cell = make_cell(name, **cfg)
     if orbitals:
-        ks_orbitals(cell, device=device, verbose=verbose)
+        ks_orbitals(cell, device=device, verbose=verbose, n_extra=n_extra)
     return cell
 
 
