@@ -146,10 +146,11 @@ def cocg_mode(precond: bool, window) -> str:
     return "precond" if window is None else f"precond_window {window[0]:g} {window[1]:g}"
 
 
-def pmc_traffic(workload, precond=False, window=None):
+def pmc_traffic(workload, precond=False, window=None, n_extra=0):
     """HBM bytes per launch of the dominant Sternheimer kernel from the
     committed rocprofv3 --pmc summary, or None when it is missing, for another
-    workload or solver mode, or for another version of the kernel source."""
+    workload, solver mode or Galerkin space, or for another version of the
+    kernel source."""
     if not os.path.exists(PMC_SUMMARY):
         return None
     vals = {}
@@ -158,7 +159,8 @@ def pmc_traffic(workload, precond=False, window=None):
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("workload") != workload or vals.get("cocg_source_sha") != source_sha() or \
-            vals.get("mode", "plain") != cocg_mode(precond, window):
+            vals.get("mode", "plain") != cocg_mode(precond, window) or \
+            int(vals.get("galerkin_extra", "0")) != int(n_extra):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -566,7 +568,7 @@ def main():
     # the preconditioned kernel is priced against whichever ceiling it is closer to
     use_mfma = "mfma" in dom and dom["mfma"]["frac"] is not None and dom["hbm_frac"] is not None \
         and dom["mfma"]["frac"] > dom["hbm_frac"]
-    traffic = pmc_traffic(args.workload, args.precond, args.precond_window) \
+    traffic = pmc_traffic(args.workload, args.precond, args.precond_window, args.extra) \
         if args.precision == "fp32_refine" else None
 
     extra = {}
