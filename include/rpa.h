@@ -83,8 +83,7 @@ typedef struct {
   int32_t slots_per_cu;       /* resident COCG workgroups per compute unit */
   double inner_tol;           /* RPA_FP32_REFINE: the FP32 recursive residual is replaced
                                  by the FP64 residual each time it drops by this
-                                 factor (reliable update); in (0, 1), 0 = 0.01 for plain
-                                 and 0.001 for preconditioned solves */
+                                 factor (reliable update); in (0, 1), 0 = 0.001 */
   int32_t use_graph;          /* != 0: lanczos_energy_density captures the per-batch
                                  launch sequence (all Lanczos steps) into a hipGraph
                                  and replays it for later batches of the same size;

@@ -879,10 +879,12 @@ rpa_status rpa_setup(const rpa_setup_params* p, void* stream, rpa_handle* out) {
   // Si64 workload 0.01 needs 3.0 updates and 98.3 iterations per solve
   // against 5.6 and 97.1 at 0.1, and each update costs about five FP32
   // iterations of time (fold plus FP64 residual sweep): 5% faster overall.
-  // defaults measured on the Si64-like workload: 0.01 for plain COCG; the
-  // preconditioned solves, a few dozen iterations each, gain from fewer
-  // updates (0.001: 2.3 instead of 2.9 per solve, 3% less kernel time)
-  h->inner_tol = p->inner_tol > 0 ? p->inner_tol : 0.01;
+  // defaults measured on the Si64-like workload: the preconditioned solves,
+  // a few dozen iterations each, gain from fewer updates (0.001: 2.3 instead
+  // of 2.9 per solve, 3% less kernel time than 0.01); so do the plain ones
+  // after the widened Galerkin guess (5% less), and the long plain solves of
+  // the occupied-only guess take the same time at 0.001 and 0.01
+  h->inner_tol = p->inner_tol > 0 ? p->inner_tol : 0.001;
   h->inner_tol_pc = p->inner_tol > 0 ? p->inner_tol : 0.001;
   h->slots_per_cu = p->slots_per_cu;
   h->use_graph = p->use_graph;
