@@ -157,6 +157,24 @@ def test_synthcell_orbitals_are_eigenpairs_of_oracle_H(tiny_cell, tiny_ops, tiny
     assert np.allclose(c.eps, ev[: c.n_occ], atol=1e-10)
 
 
+def test_synthcell_extra_eigenpairs_are_the_next_ones(tiny_cell, tiny_ops, tiny_dense):
+    """n_extra: the next eigenpairs of H above the occupied ones (the dense
+    spectrum's n_occ .. n_occ + n_extra - 1), orthonormal and orthogonal to
+    the occupied orbitals, which stay those of the plain cell."""
+    import synthcell
+    ham, _ = tiny_ops
+    ev, _ = tiny_dense
+    k = 8
+    c = synthcell.preset("tiny", n_extra=k)
+    assert c.psi_extra.shape == (k, c.N_d)
+    R = ham.apply(c.psi_extra.T).T - c.eps_extra[:, None] * c.psi_extra
+    assert np.abs(R).max() * math.sqrt(c.dV) < 1e-9
+    assert np.allclose(c.eps_extra, ev[c.n_occ:c.n_occ + k], atol=1e-10)
+    allpsi = np.vstack([c.psi, c.psi_extra])
+    assert np.allclose(c.dV * allpsi @ allpsi.T, np.eye(c.n_occ + k), atol=1e-11)
+    assert np.abs(c.eps - tiny_cell.eps).max() < 1e-12
+
+
 # --- nonlocal projectors (separable V_nl of the Background section) -------------
 
 @pytest.fixture(scope="module")
